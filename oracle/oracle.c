@@ -1,0 +1,408 @@
+/*
+ * oracle.c -- FP64 CPU oracle of the CMP / 2D-CRS semblance parameter scan.
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the package smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the HIP implementation and must never be used
+ * as a fallback for it.
+ *
+ * What it computes (Hu, Yang, Luan, Qian, "Massively Scaling Seismic
+ * Processing on Sunway TaihuLight Supercomputer"):
+ *
+ *  - the grid search of section 3.2 (Fig. 5b): for every output sample t0 of a
+ *    central gather and every candidate parameter theta, the semblance of the
+ *    traces along the traveltime curve (CMP, section 2.1) or surface (CRS,
+ *    section 2.2, where the traces of the neighbouring gathers join in);
+ *  - the semblance of Eq. (1) over a window of w samples centred on each
+ *    trace's intersection, each sample linearly interpolated with the one
+ *    fraction x of the intersection (Algorithm 1, the accumulation of _num,
+ *    _den and _ac_linear; Algorithm 2 performs the same sums trace-outer);
+ *  - the pick of the most coherent parameter per sample (section 3.2) and the
+ *    stacked amplitude along it.
+ *
+ * Readings where the paper is silent (each is listed with its reason in the
+ * design notes of the repository):
+ *  - traveltime, CMP:  T = t0^2 + q h^2, q = 4/v^2, h = half-offset;
+ *    CRS: T = (t0 + 2 A dm)^2 + 2 t0 B dm^2 + q h^2, dm = trace midpoint -
+ *    central midpoint (the paper names the curve and the surface but prints
+ *    neither formula);
+ *  - tau = sqrt(T)/dt samples, k = floor(tau), x = tau - k, window start
+ *    a = k - (w-1)/2; sample j of the window is f[a+j] + x (f[a+j+1] - f[a+j]);
+ *  - a trace contributes only if T >= 0 and 0 <= a and a + w <= ns - 1 (all
+ *    w+1 samples the window reads lie on the trace);
+ *  - S = sum_j U_j^2 / (M * D) with U_j the sum over contributing traces of
+ *    window sample j, D the sum of the squares, M the number of contributing
+ *    traces (Eq. (1) with the 1/M that makes S lie in [0, 1]); S = 0 if M = 0
+ *    or D = 0;
+ *  - stack = L / (M w), L the sum of all window samples (the _ac_linear sum);
+ *    stack = 0 if M = 0;
+ *  - the pick is the smallest flat parameter index reaching the maximum S;
+ *    flat index = (iA * nB + iB) * nq + iq.
+ *
+ * Pins (tests that fix this code against something other than itself):
+ * closed forms at zero moveout, ramp traces, integer-aligned single-event
+ * Ricker gathers, invariants (0 <= S <= 1, scale and permutation invariance,
+ * CRS with A = B = 0 equals CMP), an independent brute force on tiny
+ * gathers, and finite differences for the gradient.  The stack formula, the
+ * window-edge rule and the tie-break are readings: the tests pin the code to
+ * those readings, the paper does not fix them.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_CMP 0
+#define ORACLE_CRS 1
+
+/* Perturbations used to flag cells whose set of contributing traces could
+ * differ between FP64 and FP32 arithmetic. */
+#define FRAGILE_TAU 1e-3    /* samples */
+#define FRAGILE_T_REL 1e-6  /* relative to the magnitude of T's terms */
+
+typedef struct {
+    const float *samples;
+    const int64_t *sample_off;
+    const int32_t *trace_ptr;
+    const int32_t *ns;
+    const float *half_offset;
+    const float *midpoint;
+    const float *central_x;
+    double dt;
+} gset;
+
+typedef struct {
+    double A, B, q;
+} theta_t;
+
+/* Squared traveltime (s^2) of trace i of the aperture for parameter th.  Also
+ * returns the sum of the magnitudes of its terms (for the fragility test). */
+static double traveltime_sq(int kind, double t0, theta_t th, double dm, double h, double *mag)
+{
+    if (kind == ORACLE_CMP) {
+        *mag = t0 * t0 + fabs(th.q * h * h);
+        return t0 * t0 + th.q * h * h;
+    }
+    double y = t0 + 2.0 * th.A * dm;
+    double b = 2.0 * t0 * th.B * dm * dm;
+    double c = th.q * h * h;
+    *mag = y * y + fabs(b) + fabs(c);
+    return y * y + b + c;
+}
+
+/* Is a window starting at sample a = floor(tau) - hw entirely on a trace of
+ * ns samples? */
+static int window_on_trace(double tau, int w, int ns)
+{
+    int hw = (w - 1) / 2;
+    double kf = floor(tau);
+    double a = kf - hw;
+    return a >= 0.0 && a + w <= (double)(ns - 1);
+}
+
+typedef struct {
+    double S, stack, D, N, L;
+    int M;
+    int fragile;
+} cell_t;
+
+/* The accumulators of one (job, t0, theta) cell, traces in ascending order:
+ * U[w], D, L and M (Algorithm 1's _num, _den, _ac_linear plus the trace count). */
+static cell_t eval_cell(const gset *g, int kind, int central, const int32_t *ag, int na,
+                        int s, theta_t th, int w, double *U)
+{
+    cell_t c = {0};
+    const int hw = (w - 1) / 2;
+    const double t0 = s * g->dt;
+    const double xc = (kind == ORACLE_CRS) ? (double)g->central_x[central] : 0.0;
+    for (int j = 0; j < w; j++) U[j] = 0.0;
+
+    for (int p = 0; p < na; p++) {
+        const int gg = ag[p];
+        const int nsg = g->ns[gg];
+        for (int i = g->trace_ptr[gg]; i < g->trace_ptr[gg + 1]; i++) {
+            const float *f = g->samples + g->sample_off[gg] + (int64_t)(i - g->trace_ptr[gg]) * nsg;
+            const double h = g->half_offset[i];
+            const double dm = (kind == ORACLE_CRS) ? (double)g->midpoint[i] - xc : 0.0;
+            double mag;
+            const double T = traveltime_sq(kind, t0, th, dm, h, &mag);
+
+            /* fragility: would a tiny change of T or tau change whether this
+             * trace contributes? */
+            const double dT = FRAGILE_T_REL * mag;
+            if (fabs(T) <= dT) {
+                int v_lo = (T - dT >= 0.0) && window_on_trace(sqrt(T - dT) / g->dt, w, nsg);
+                int v_hi = (T + dT >= 0.0) && window_on_trace(sqrt(T + dT) / g->dt, w, nsg);
+                if (v_lo != v_hi) c.fragile = 1;
+            }
+            if (T < 0.0) continue;
+            const double tau = sqrt(T) / g->dt;
+            const int valid = window_on_trace(tau, w, nsg);
+            if (window_on_trace(tau - FRAGILE_TAU, w, nsg) != valid ||
+                window_on_trace(tau + FRAGILE_TAU, w, nsg) != valid)
+                c.fragile = 1;
+            if (!valid) continue;
+
+            const double kf = floor(tau);
+            const double x = tau - kf;
+            const int64_t a = (int64_t)kf - hw;
+            for (int j = 0; j < w; j++) {
+                const double f0 = f[a + j], f1 = f[a + j + 1];
+                const double v = f0 + x * (f1 - f0);
+                U[j] += v;
+                c.D += v * v;
+                c.L += v;
+            }
+            c.M += 1;
+        }
+    }
+    for (int j = 0; j < w; j++) c.N += U[j] * U[j];
+    c.S = (c.M > 0 && c.D > 0.0) ? c.N / ((double)c.M * c.D) : 0.0;
+    c.stack = (c.M > 0) ? c.L / ((double)c.M * (double)w) : 0.0;
+    return c;
+}
+
+/* Row r of the output -> (job, sample). */
+typedef struct {
+    int32_t job, s;
+} row_t;
+
+static row_t *make_rows(const gset *g, int32_t njobs, const int32_t *job_central, int64_t *nrows)
+{
+    int64_t n = 0;
+    for (int j = 0; j < njobs; j++) n += g->ns[job_central[j]];
+    row_t *rows = (row_t *)malloc(sizeof(row_t) * (size_t)(n > 0 ? n : 1));
+    int64_t r = 0;
+    for (int j = 0; j < njobs; j++)
+        for (int s = 0; s < g->ns[job_central[j]]; s++) {
+            rows[r].job = j;
+            rows[r].s = s;
+            r++;
+        }
+    *nrows = n;
+    return rows;
+}
+
+static int check_args(int kind, const gset *g, int w, int nA, int nB, int nq)
+{
+    if (kind != ORACLE_CMP && kind != ORACLE_CRS) return 1;
+    if (w < 1 || (w % 2) == 0) return 1;
+    if (nA < 1 || nB < 1 || nq < 1) return 1;
+    if (!(g->dt > 0.0)) return 1;
+    if (kind == ORACLE_CRS && (!g->midpoint || !g->central_x)) return 1;
+    return 0;
+}
+
+/*
+ * Exhaustive scan (section 3.2): for every job, output sample and flat
+ * parameter index, the semblance; then per output row the pick, its
+ * semblance and its stack.  Optional outputs: panel (row-major [row][param]),
+ * gap (best S minus the best S of any other parameter) and fragile (1 if any
+ * cell of the row is fragile).  Output row of (job j, sample s) is
+ * out_off[j] + s.  Returns 0, or 1 for invalid arguments.
+ */
+int oracle_scan(int kind, const float *samples, const int64_t *sample_off, const int32_t *trace_ptr,
+                const int32_t *ns, const float *half_offset, const float *midpoint,
+                const float *central_x, double dt, int32_t njobs, const int32_t *job_central,
+                const int32_t *apert_ptr, const int32_t *apert_gather, const int64_t *out_off,
+                const float *A, int32_t nA, const float *B, int32_t nB, const float *q, int32_t nq,
+                int32_t w, int32_t *best, double *s_best, double *stack, double *panel, double *gap,
+                uint8_t *fragile, int nthreads)
+{
+    gset g = {samples, sample_off, trace_ptr, ns, half_offset, midpoint, central_x, dt};
+    if (check_args(kind, &g, w, nA, nB, nq)) return 1;
+    if (kind == ORACLE_CMP) nA = nB = 1;
+    const int64_t npar = (int64_t)nA * nB * nq;
+    int64_t nrows;
+    row_t *rows = make_rows(&g, njobs, job_central, &nrows);
+    if (nthreads < 1) nthreads = 1;
+
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+    for (int64_t r = 0; r < nrows; r++) {
+        double U[64];
+        double *Ub = (w <= 64) ? U : (double *)malloc(sizeof(double) * (size_t)w);
+        const int j = rows[r].job, s = rows[r].s;
+        const int64_t orow = out_off[j] + s;
+        const int c = job_central[j];
+        const int32_t *ag = apert_gather + apert_ptr[j];
+        const int na = apert_ptr[j + 1] - apert_ptr[j];
+        double s1 = -1.0, s2 = -1.0, st1 = 0.0;
+        int64_t p1 = 0;
+        int frag = 0;
+        for (int iA = 0; iA < nA; iA++)
+            for (int iB = 0; iB < nB; iB++)
+                for (int iq = 0; iq < nq; iq++) {
+                    theta_t th;
+                    th.A = (kind == ORACLE_CRS) ? (double)A[iA] : 0.0;
+                    th.B = (kind == ORACLE_CRS) ? (double)B[iB] : 0.0;
+                    th.q = q[iq];
+                    const int64_t p = ((int64_t)iA * nB + iB) * nq + iq;
+                    cell_t cl = eval_cell(&g, kind, c, ag, na, s, th, w, Ub);
+                    frag |= cl.fragile;
+                    if (panel) panel[orow * npar + p] = cl.S;
+                    if (cl.S > s1) { /* strict: the first index wins ties */
+                        s2 = s1;
+                        s1 = cl.S;
+                        st1 = cl.stack;
+                        p1 = p;
+                    } else if (cl.S > s2) {
+                        s2 = cl.S;
+                    }
+                }
+        best[orow] = (int32_t)p1;
+        s_best[orow] = s1;
+        stack[orow] = st1;
+        if (gap) gap[orow] = (npar > 1) ? s1 - s2 : INFINITY;
+        if (fragile) fragile[orow] = (uint8_t)frag;
+        if (Ub != U) free(Ub);
+    }
+    free(rows);
+    return 0;
+}
+
+/*
+ * Point evaluation: semblance and stack of every output row at its own
+ * parameter theta[row] = (A, B, q) (CMP ignores A and B).  Optional per-row
+ * contributing-trace count M and fragility flag.
+ */
+int oracle_point(int kind, const float *samples, const int64_t *sample_off, const int32_t *trace_ptr,
+                 const int32_t *ns, const float *half_offset, const float *midpoint,
+                 const float *central_x, double dt, int32_t njobs, const int32_t *job_central,
+                 const int32_t *apert_ptr, const int32_t *apert_gather, const int64_t *out_off,
+                 const double *theta, int32_t w, double *s_out, double *stack_out, int32_t *m_out,
+                 uint8_t *fragile, int nthreads)
+{
+    gset g = {samples, sample_off, trace_ptr, ns, half_offset, midpoint, central_x, dt};
+    if (check_args(kind, &g, w, 1, 1, 1)) return 1;
+    int64_t nrows;
+    row_t *rows = make_rows(&g, njobs, job_central, &nrows);
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+    for (int64_t r = 0; r < nrows; r++) {
+        double U[64];
+        double *Ub = (w <= 64) ? U : (double *)malloc(sizeof(double) * (size_t)w);
+        const int j = rows[r].job, s = rows[r].s;
+        const int64_t orow = out_off[j] + s;
+        theta_t th = {theta[3 * orow + 0], theta[3 * orow + 1], theta[3 * orow + 2]};
+        if (kind == ORACLE_CMP) th.A = th.B = 0.0;
+        cell_t cl = eval_cell(&g, kind, job_central[j], apert_gather + apert_ptr[j],
+                              apert_ptr[j + 1] - apert_ptr[j], s, th, w, Ub);
+        s_out[orow] = cl.S;
+        stack_out[orow] = cl.stack;
+        if (m_out) m_out[orow] = cl.M;
+        if (fragile) fragile[orow] = (uint8_t)cl.fragile;
+        if (Ub != U) free(Ub);
+    }
+    free(rows);
+    return 0;
+}
+
+/*
+ * Gradient of L = sum_rows g_s[row] * S(row, theta[row]) with respect to
+ * theta (overwritten, [row][3] = dL/dA, dL/dB, dL/dq) and, if g_samples is
+ * not NULL, with respect to every sample (ACCUMULATED into g_samples, same
+ * layout as samples).
+ *
+ * With the contributing set and every window start a held fixed (they are
+ * piecewise constant in theta and the samples):
+ *   dS/dv_ij   = 2 (U_j - S M v_ij) / (M D)
+ *   dv_ij/dtau = f[a+j+1] - f[a+j]            (slope of the segment used)
+ *   dtau/dT    = 1 / (2 dt sqrt(T))
+ *   dT/dA = 4 dm (t0 + 2 A dm),  dT/dB = 2 t0 dm^2,  dT/dq = h^2
+ *   dv_ij/df[a+j] = 1 - x,  dv_ij/df[a+j+1] = x.
+ * Rows with M = 0 or D = 0 (S identically 0) and traces with T = 0 (tau has
+ * no derivative there) contribute nothing.
+ */
+int oracle_grad(int kind, const float *samples, const int64_t *sample_off, const int32_t *trace_ptr,
+                const int32_t *ns, const float *half_offset, const float *midpoint,
+                const float *central_x, double dt, int32_t njobs, const int32_t *job_central,
+                const int32_t *apert_ptr, const int32_t *apert_gather, const int64_t *out_off,
+                const double *theta, const double *g_s, int32_t w, double *g_theta,
+                double *g_samples, int nthreads)
+{
+    gset g = {samples, sample_off, trace_ptr, ns, half_offset, midpoint, central_x, dt};
+    if (check_args(kind, &g, w, 1, 1, 1)) return 1;
+    int64_t nrows;
+    row_t *rows = make_rows(&g, njobs, job_central, &nrows);
+    if (nthreads < 1) nthreads = 1;
+    const int hw = (w - 1) / 2;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+    for (int64_t r = 0; r < nrows; r++) {
+        double U[64];
+        double *Ub = (w <= 64) ? U : (double *)malloc(sizeof(double) * (size_t)w);
+        const int j = rows[r].job, s = rows[r].s;
+        const int64_t orow = out_off[j] + s;
+        const int c = job_central[j];
+        const int32_t *ag = apert_gather + apert_ptr[j];
+        const int na = apert_ptr[j + 1] - apert_ptr[j];
+        theta_t th = {theta[3 * orow + 0], theta[3 * orow + 1], theta[3 * orow + 2]};
+        if (kind == ORACLE_CMP) th.A = th.B = 0.0;
+        double gA = 0.0, gB = 0.0, gq = 0.0;
+        cell_t cl = eval_cell(&g, kind, c, ag, na, s, th, w, Ub);
+        const double gs = g_s[orow];
+        if (cl.M > 0 && cl.D > 0.0 && gs != 0.0) {
+            const double t0 = s * dt;
+            const double xc = (kind == ORACLE_CRS) ? (double)central_x[c] : 0.0;
+            const double MD = (double)cl.M * cl.D;
+            for (int p = 0; p < na; p++) {
+                const int gg = ag[p];
+                const int nsg = ns[gg];
+                for (int i = trace_ptr[gg]; i < trace_ptr[gg + 1]; i++) {
+                    const int64_t base = sample_off[gg] + (int64_t)(i - trace_ptr[gg]) * nsg;
+                    const float *f = samples + base;
+                    const double h = half_offset[i];
+                    const double dm = (kind == ORACLE_CRS) ? (double)midpoint[i] - xc : 0.0;
+                    double mag;
+                    const double T = traveltime_sq(kind, t0, th, dm, h, &mag);
+                    if (T < 0.0) continue;
+                    const double tau = sqrt(T) / dt;
+                    if (!window_on_trace(tau, w, nsg)) continue;
+                    const double kf = floor(tau);
+                    const double x = tau - kf;
+                    const int64_t a = (int64_t)kf - hw;
+                    double dS_dtau = 0.0;
+                    for (int jj = 0; jj < w; jj++) {
+                        const double f0 = f[a + jj], f1 = f[a + jj + 1];
+                        const double v = f0 + x * (f1 - f0);
+                        const double dS_dv = 2.0 * (Ub[jj] - cl.S * cl.M * v) / MD;
+                        dS_dtau += dS_dv * (f1 - f0);
+                        if (g_samples) {
+#pragma omp atomic
+                            g_samples[base + a + jj] += gs * (1.0 - x) * dS_dv;
+#pragma omp atomic
+                            g_samples[base + a + jj + 1] += gs * x * dS_dv;
+                        }
+                    }
+                    if (T > 0.0) {
+                        const double dtau_dT = 1.0 / (2.0 * dt * sqrt(T));
+                        if (kind == ORACLE_CRS) {
+                            gA += dS_dtau * dtau_dT * 4.0 * dm * (t0 + 2.0 * th.A * dm);
+                            gB += dS_dtau * dtau_dT * 2.0 * t0 * dm * dm;
+                        }
+                        gq += dS_dtau * dtau_dT * h * h;
+                    }
+                }
+            }
+        }
+        g_theta[3 * orow + 0] = gs * gA;
+        g_theta[3 * orow + 1] = gs * gB;
+        g_theta[3 * orow + 2] = gs * gq;
+        if (Ub != U) free(Ub);
+    }
+    free(rows);
+    return 0;
+}
+
+/* Number of OpenMP threads a parallel region would get (1 without OpenMP). */
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
