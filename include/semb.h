@@ -1,0 +1,173 @@
+/*
+ * semb.h -- C ABI of the MI355X (gfx950) semblance parameter-scan library.
+ *
+ * The operations are those of Hu, Yang, Luan and Qian, "Massively Scaling
+ * Seismic Processing on Sunway TaihuLight Supercomputer":
+ *
+ *   cmp_scan        exhaustive CMP velocity scan (section 2.1 and the grid
+ *                   search of section 3.2): for every output sample t0 of a
+ *                   gather and every candidate q = 4/v^2, the semblance of
+ *                   Eq. (1) over a w-sample window centred on each trace's
+ *                   intersection with the traveltime curve, linearly
+ *                   interpolated (Algorithm 1); then the most coherent
+ *                   parameter per sample and the stacked amplitude along it.
+ *   crs_scan        the same for the 2D CRS method (section 2.2): the traces
+ *                   of the neighbouring gathers join the central gather's and
+ *                   the curve becomes a surface in (A, B, q).
+ *   stack           semblance and stack at one given parameter per output
+ *                   sample (the same sums as above, evaluated once).
+ *   semblance_grad  gradient of sum_rows g_s[row] * S(row) with respect to
+ *                   each row's parameter and to every input sample.
+ *
+ * Definitions shared by every call (readings of the paper that it does not
+ * spell out):
+ *   t0 = s * dt for output sample s = 0 .. ns[central]-1;
+ *   CMP traveltime  T = t0^2 + q h^2;
+ *   CRS traveltime  T = (t0 + 2 A dm)^2 + 2 t0 B dm^2 + q h^2, dm = midpoint of
+ *                   the trace - central_x of the job's central gather;
+ *   tau = sqrt(T)/dt, k = floor(tau), x = tau - k, window start a = k - (w-1)/2,
+ *   window sample j = f[a+j] + x (f[a+j+1] - f[a+j]), j = 0 .. w-1;
+ *   a trace contributes only if T >= 0, a >= 0 and a + w <= ns - 1 (its own ns);
+ *   S = sum_j U_j^2 / (M D), U_j = sum of window sample j over contributing
+ *   traces, D = sum of their squares, M = number of contributing traces;
+ *   S = 0 when M = 0 or D = 0;  stack = (sum_j U_j) / (M w), 0 when M = 0;
+ *   pick = smallest flat parameter index reaching the maximum S, with
+ *   flat = (iA * nB + iB) * nq + iq  (CMP: flat = iq).
+ *
+ * Conventions:
+ *   - Every pointer is DEVICE memory unless marked [host].  The caller owns
+ *     every buffer; the library never allocates or frees device memory and
+ *     never synchronises: each call only enqueues work on `stream` and
+ *     returns.  Results are valid once the stream has reached that point.
+ *   - Arguments are validated on the host before anything is enqueued;
+ *     invalid ones return SEMB_EINVAL, a too small workspace
+ *     SEMB_EWORKSPACE, and a failed launch SEMB_EHIP.  semb_last_error()
+ *     then holds a message (per thread).  Data-dependent conditions (T < 0,
+ *     windows off the trace, M = 0, D = 0) are not errors: they have the
+ *     results defined above.
+ *   - Device contents are not inspected on the host.  The host-side bounds
+ *     in semb_gathers (ns_max, nsamples) must hold for the device arrays;
+ *     rows beyond ns_max are not computed, and the kernels never read
+ *     outside [0, nsamples) or outside a trace.
+ */
+#ifndef SEMB_H
+#define SEMB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SEMB_OK = 0,
+    SEMB_EINVAL = 1,     /* invalid argument; nothing was enqueued            */
+    SEMB_EWORKSPACE = 2, /* workspace missing or smaller than required        */
+    SEMB_EHIP = 3        /* a HIP launch failed; see semb_last_error()        */
+} semb_status;
+
+enum { SEMB_KIND_CMP = 0, SEMB_KIND_CRS = 1 };
+
+/* Seismic gathers (the CDP data structure of section 3.2, Fig. 5a): gather g
+ * owns traces trace_ptr[g] .. trace_ptr[g+1]-1, stored consecutively from
+ * element sample_off[g] of `samples`, each ns[g] samples long (sample n at
+ * time n*dt).  The struct itself is [host]; its array pointers are device
+ * pointers. */
+typedef struct semb_gathers {
+    const float *samples;     /* FP32 [nsamples]                                     */
+    const int64_t *sample_off; /* [ngathers] first element of gather g              */
+    const int32_t *trace_ptr; /* [ngathers + 1], trace_ptr[0] = 0                    */
+    const int32_t *ns;        /* [ngathers] samples per trace of gather g, >= 1       */
+    const float *half_offset; /* [ntraces] h, metres (the paper's "halfpoints")      */
+    const float *midpoint;    /* [ntraces] midpoint coordinate, metres (CRS only;
+                                 may be NULL for CMP calls)                          */
+    const float *central_x;   /* [ngathers] coordinate of gather g's midpoint, metres
+                                 (CRS only; may be NULL for CMP calls)               */
+    int32_t ngathers;
+    int32_t ntraces;
+    int32_t ns_max;           /* [host] upper bound of ns[]; 1 .. SEMB_NS_LIMIT      */
+    int64_t nsamples;         /* [host] number of elements of samples                */
+    float dt;                 /* [host] sampling interval, seconds, > 0              */
+} semb_gathers;
+
+/* Scan jobs.  Job j stacks at gather central[j]; its traces are those of the
+ * gathers apert_gather[apert_ptr[j] .. apert_ptr[j+1]-1] in that order (for a
+ * CMP job just the central gather; apert_ptr/apert_gather may then be NULL).
+ * Output row of (job j, sample s) is out_off[j] + s. */
+typedef struct semb_jobs {
+    const int32_t *central;      /* [njobs]                                           */
+    const int32_t *apert_ptr;    /* [njobs + 1] or NULL (CMP)                          */
+    const int32_t *apert_gather; /* [apert_ptr[njobs]] or NULL (CMP)                   */
+    const int64_t *out_off;      /* [njobs]                                           */
+    int32_t njobs;               /* [host] >= 0                                       */
+    int32_t max_apert;           /* [host] upper bound of gathers per aperture
+                                    (1 for CMP), 1 .. SEMB_APERT_LIMIT                */
+    int64_t n_out;               /* [host] number of output rows (>= every
+                                    out_off[j] + ns[central[j]])                      */
+} semb_jobs;
+
+/* Outputs of a scan, one element per output row (panel: n_params per row,
+ * row-major).  All are fully overwritten for the rows the jobs cover. */
+typedef struct semb_outputs {
+    int32_t *best;  /* [n_out] flat index of the picked parameter                  */
+    float *s_best;  /* [n_out] its semblance                                        */
+    float *stack;   /* [n_out] its stacked amplitude                                */
+    float *panel;   /* [n_out * n_params] every semblance, or NULL                  */
+} semb_outputs;
+
+#define SEMB_W_MAX 31          /* largest window; w must be odd, 1 .. SEMB_W_MAX */
+#define SEMB_NS_LIMIT 2048     /* largest samples per trace (LDS stage capacity)  */
+#define SEMB_APERT_LIMIT 64    /* largest number of gathers in one aperture        */
+
+/* Workspace (device bytes) that cmp_scan / crs_scan need for gathers with
+ * `nsamples` elements.  [host] */
+size_t semb_workspace_bytes(int64_t nsamples);
+
+/* CMP scan (section 2.1; grid search of section 3.2).  q[nq]: candidates
+ * q = 4/v^2 in s^2/m^2.  w: window length in samples (odd).  ws: workspace of
+ * at least semb_workspace_bytes(g->nsamples) bytes, 256-byte aligned; its
+ * contents are scratch. */
+semb_status cmp_scan(const semb_gathers *g, const semb_jobs *jobs, const float *q, int32_t nq,
+                     int32_t w, const semb_outputs *out, void *ws, size_t ws_bytes,
+                     hipStream_t stream);
+
+/* 2D CRS scan (section 2.2 with the same grid search).  A[nA] in s/m, B[nB]
+ * in s/m^2, q[nq] in s^2/m^2; n_params = nA * nB * nq, flat index
+ * (iA * nB + iB) * nq + iq.  Requires g->midpoint and g->central_x. */
+semb_status crs_scan(const semb_gathers *g, const semb_jobs *jobs, const float *A, int32_t nA,
+                     const float *B, int32_t nB, const float *q, int32_t nq, int32_t w,
+                     const semb_outputs *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Semblance and stack of every output row at its own parameter theta[row] =
+ * (A, B, q) (FP32 [n_out][3]; CMP ignores A and B).  s_out, stack_out:
+ * [n_out], overwritten. */
+semb_status stack(const semb_gathers *g, const semb_jobs *jobs, int32_t kind, const float *theta,
+                  int32_t w, float *s_out, float *stack_out, hipStream_t stream);
+
+/* Gradient of L = sum_rows g_s[row] * S(row, theta[row]).  g_theta [n_out][3]
+ * is overwritten with dL/dA, dL/dB, dL/dq (zero for CMP's A and B).
+ * g_samples (nullable, [nsamples]) is ACCUMULATED into (+=), as autograd
+ * accumulates gradients; the caller clears it.  With every contributing set
+ * and window start held fixed (they are piecewise constant): dS/dv_ij =
+ * 2 (U_j - S M v_ij) / (M D), dv_ij/dtau = f[a+j+1] - f[a+j],
+ * dtau/dT = 1 / (2 dt sqrt T), dT/dA = 4 dm (t0 + 2 A dm), dT/dB = 2 t0 dm^2,
+ * dT/dq = h^2, dv_ij/df[a+j] = 1 - x, dv_ij/df[a+j+1] = x.  Rows with
+ * M = 0 or D = 0 and traces with T = 0 contribute nothing. */
+semb_status semblance_grad(const semb_gathers *g, const semb_jobs *jobs, int32_t kind,
+                           const float *theta, const float *g_s, int32_t w, float *g_theta,
+                           float *g_samples, hipStream_t stream);
+
+/* Message describing the last non-OK status returned on this thread. [host] */
+const char *semb_last_error(void);
+
+/* Library version string. [host] */
+const char *semb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEMB_H */

@@ -47,7 +47,9 @@ class Library:
         L.oracle_scan.argtypes = common + [P, i32, P, i32, P, i32, i32, P, P, P, P, P, P, C.c_int]
         L.oracle_point.argtypes = common + [P, i32, P, P, P, P, C.c_int]
         L.oracle_grad.argtypes = common + [P, P, i32, P, P, C.c_int]
-        for f in (L.oracle_scan, L.oracle_point, L.oracle_grad):
+        L.oracle_scan_rows.argtypes = [C.c_int, P, P, P, P, P, P, P, f64, i32, P, P, P, P, P,
+                                       P, i32, P, i32, P, i32, i32, P, P, P, P, P, C.c_int]
+        for f in (L.oracle_scan, L.oracle_point, L.oracle_grad, L.oracle_scan_rows):
             f.restype = C.c_int
         L.oracle_max_threads.restype = C.c_int
         self.L = L
@@ -144,6 +146,31 @@ def scan(kind, gs, jobs, grid, w: int, panel: bool = False, nthreads: int | None
     if rc != 0:
         raise ValueError("oracle_scan: invalid arguments")
     return ScanResult(best, sb, st, gap, fr.astype(bool), pan)
+
+
+def scan_rows(kind, gs, jobs, grid, w: int, row_job, row_s, nthreads: int | None = None,
+              library: Library | None = None) -> ScanResult:
+    """The exhaustive scan for selected output rows (row r = sample row_s[r] of
+    job row_job[r]); results are indexed by r (panel is None)."""
+    a = _Args(kind, gs, jobs)
+    rj = _c(row_job, np.int32)
+    rs = _c(row_s, np.int32)
+    n = rj.size
+    A, B, q = _c(grid.A, np.float32), _c(grid.B, np.float32), _c(grid.q, np.float32)
+    best = np.zeros(n, np.int32)
+    sb = np.zeros(n, np.float64)
+    st = np.zeros(n, np.float64)
+    gap = np.zeros(n, np.float64)
+    fr = np.zeros(n, np.uint8)
+    k = a.keep
+    j = a.jobs
+    rc = (library or lib()).L.oracle_scan_rows(
+        a.kind, _p(k[0]), _p(k[1]), _p(k[2]), _p(k[3]), _p(k[4]), _p(k[5]), _p(k[6]), a.dt, n,
+        _p(rj), _p(rs), _p(j[0]), _p(j[1]), _p(j[2]), _p(A), A.size, _p(B), B.size, _p(q), q.size,
+        int(w), _p(best), _p(sb), _p(st), _p(gap), _p(fr), int(nthreads or max_threads()))
+    if rc != 0:
+        raise ValueError("oracle_scan_rows: invalid arguments")
+    return ScanResult(best, sb, st, gap, fr.astype(bool), None)
 
 
 def point(kind, gs, jobs, theta: np.ndarray, w: int, nthreads: int | None = None,

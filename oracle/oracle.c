@@ -265,6 +265,61 @@ int oracle_scan(int kind, const float *samples, const int64_t *sample_off, const
 }
 
 /*
+ * The same exhaustive scan restricted to an explicit list of output rows
+ * (row r = sample row_s[r] of job row_job[r]); outputs are indexed by r.
+ * Lets a test check sampled rows of a workload too large to scan in full.
+ */
+int oracle_scan_rows(int kind, const float *samples, const int64_t *sample_off, const int32_t *trace_ptr,
+                     const int32_t *ns, const float *half_offset, const float *midpoint,
+                     const float *central_x, double dt, int32_t nrows, const int32_t *row_job,
+                     const int32_t *row_s, const int32_t *job_central, const int32_t *apert_ptr,
+                     const int32_t *apert_gather, const float *A, int32_t nA, const float *B, int32_t nB,
+                     const float *q, int32_t nq, int32_t w, int32_t *best, double *s_best, double *stack,
+                     double *gap, uint8_t *fragile, int nthreads)
+{
+    gset g = {samples, sample_off, trace_ptr, ns, half_offset, midpoint, central_x, dt};
+    if (check_args(kind, &g, w, nA, nB, nq)) return 1;
+    if (kind == ORACLE_CMP) nA = nB = 1;
+    const int64_t npar = (int64_t)nA * nB * nq;
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (int64_t r = 0; r < nrows; r++) {
+        double U[64];
+        double *Ub = (w <= 64) ? U : (double *)malloc(sizeof(double) * (size_t)w);
+        const int j = row_job[r], s = row_s[r];
+        const int c = job_central[j];
+        const int32_t *ag = apert_gather + apert_ptr[j];
+        const int na = apert_ptr[j + 1] - apert_ptr[j];
+        double s1 = -1.0, s2 = -1.0, st1 = 0.0;
+        int64_t p1 = 0;
+        int frag = 0;
+        for (int64_t p = 0; p < npar; p++) {
+            theta_t th;
+            th.q = q[p % nq];
+            th.B = (kind == ORACLE_CRS) ? (double)B[(p / nq) % nB] : 0.0;
+            th.A = (kind == ORACLE_CRS) ? (double)A[p / ((int64_t)nq * nB)] : 0.0;
+            cell_t cl = eval_cell(&g, kind, c, ag, na, s, th, w, Ub);
+            frag |= cl.fragile;
+            if (cl.S > s1) {
+                s2 = s1;
+                s1 = cl.S;
+                st1 = cl.stack;
+                p1 = p;
+            } else if (cl.S > s2) {
+                s2 = cl.S;
+            }
+        }
+        best[r] = (int32_t)p1;
+        s_best[r] = s1;
+        stack[r] = st1;
+        if (gap) gap[r] = (npar > 1) ? s1 - s2 : INFINITY;
+        if (fragile) fragile[r] = (uint8_t)frag;
+        if (Ub != U) free(Ub);
+    }
+    return 0;
+}
+
+/*
  * Point evaluation: semblance and stack of every output row at its own
  * parameter theta[row] = (A, B, q) (CMP ignores A and B).  Optional per-row
  * contributing-trace count M and fragility flag.

@@ -1,0 +1,278 @@
+"""MI355X-native semblance parameter scan (CMP and 2D CRS).
+
+Thin Python binding of ``libsemb.so`` (HIP kernels for gfx950 behind the C
+ABI in ``include/semb.h``).  Every step of the computation runs in those
+kernels; this module only marshals arguments: torch tensors provide device
+memory and the current HIP stream, and their pointers are handed to the C
+functions of the same names (``cmp_scan``, ``crs_scan``, ``stack``,
+``semblance_grad``).  There is no CPU fallback: if the library is missing
+or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsemb.so")
+
+KIND_CMP, KIND_CRS = 0, 1
+W_MAX = 31
+NS_LIMIT = 2048
+APERT_LIMIT = 64
+_STATUS = {0: "SEMB_OK", 1: "SEMB_EINVAL", 2: "SEMB_EWORKSPACE", 3: "SEMB_EHIP"}
+
+
+class SembError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+# ---------------------------------------------------------------------------
+# C structs (mirror include/semb.h)
+# ---------------------------------------------------------------------------
+class CGathers(C.Structure):
+    _fields_ = [("samples", C.c_void_p), ("sample_off", C.c_void_p), ("trace_ptr", C.c_void_p),
+                ("ns", C.c_void_p), ("half_offset", C.c_void_p), ("midpoint", C.c_void_p),
+                ("central_x", C.c_void_p), ("ngathers", C.c_int32), ("ntraces", C.c_int32),
+                ("ns_max", C.c_int32), ("nsamples", C.c_int64), ("dt", C.c_float)]
+
+
+class CJobs(C.Structure):
+    _fields_ = [("central", C.c_void_p), ("apert_ptr", C.c_void_p), ("apert_gather", C.c_void_p),
+                ("out_off", C.c_void_p), ("njobs", C.c_int32), ("max_apert", C.c_int32),
+                ("n_out", C.c_int64)]
+
+
+class COutputs(C.Structure):
+    _fields_ = [("best", C.c_void_p), ("s_best", C.c_void_p), ("stack", C.c_void_p),
+                ("panel", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libsemb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with "
+                              "`python -m paper_1907_11678_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.semb_workspace_bytes.argtypes = [i64]
+        L.semb_workspace_bytes.restype = C.c_size_t
+        L.cmp_scan.argtypes = [P, P, P, i32, i32, P, P, C.c_size_t, P]
+        L.crs_scan.argtypes = [P, P, P, i32, P, i32, P, i32, i32, P, P, C.c_size_t, P]
+        L.stack.argtypes = [P, P, i32, P, i32, P, P, P]
+        L.semblance_grad.argtypes = [P, P, i32, P, P, i32, P, P, P]
+        for f in (L.cmp_scan, L.crs_scan, L.stack, L.semblance_grad):
+            f.restype = C.c_int
+        L.semb_last_error.restype = C.c_char_p
+        L.semb_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().semb_last_error().decode()
+
+
+def version() -> str:
+    return lib().semb_version().decode()
+
+
+def workspace_bytes(nsamples: int) -> int:
+    return int(lib().semb_workspace_bytes(int(nsamples)))
+
+
+def _check(status: int):
+    if status != 0:
+        raise SembError(status, last_error())
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _typed(t, dtype, name):
+    if t is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return _ptr(t)
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# device-resident inputs
+# ---------------------------------------------------------------------------
+@dataclass
+class DeviceGathers:
+    """Gathers resident in device memory (see ``include/semb.h``)."""
+    samples: object
+    sample_off: object
+    trace_ptr: object
+    ns: object
+    half_offset: object
+    midpoint: object
+    central_x: object
+    ns_max: int
+    dt: float
+
+    @property
+    def ngathers(self) -> int:
+        return int(self.ns.numel())
+
+    @property
+    def ntraces(self) -> int:
+        return int(self.half_offset.numel())
+
+    @property
+    def nsamples(self) -> int:
+        return int(self.samples.numel())
+
+    def cstruct(self) -> CGathers:
+        import torch
+        return CGathers(_typed(self.samples, torch.float32, "samples"),
+                        _typed(self.sample_off, torch.int64, "sample_off"),
+                        _typed(self.trace_ptr, torch.int32, "trace_ptr"),
+                        _typed(self.ns, torch.int32, "ns"),
+                        _typed(self.half_offset, torch.float32, "half_offset"),
+                        _typed(self.midpoint, torch.float32, "midpoint"),
+                        _typed(self.central_x, torch.float32, "central_x"),
+                        self.ngathers, self.ntraces, int(self.ns_max), self.nsamples, float(self.dt))
+
+
+@dataclass
+class DeviceJobs:
+    central: object
+    apert_ptr: object
+    apert_gather: object
+    out_off: object
+    max_apert: int
+    n_out: int
+
+    @property
+    def njobs(self) -> int:
+        return int(self.central.numel())
+
+    def cstruct(self) -> CJobs:
+        import torch
+        return CJobs(_typed(self.central, torch.int32, "central"),
+                     _typed(self.apert_ptr, torch.int32, "apert_ptr"),
+                     _typed(self.apert_gather, torch.int32, "apert_gather"),
+                     _typed(self.out_off, torch.int64, "out_off"),
+                     self.njobs, int(self.max_apert), int(self.n_out))
+
+
+def upload_gathers(samples, sample_off, trace_ptr, ns, half_offset, midpoint, central_x, dt,
+                   device="cuda") -> DeviceGathers:
+    """Copy host arrays (numpy or torch) to the device with the ABI's dtypes."""
+    import torch
+
+    def t(a, dt_):
+        if a is None:
+            return None
+        if isinstance(a, torch.Tensor):
+            return a.to(device=device, dtype=dt_).contiguous()
+        return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt_)
+
+    ns_host = np.asarray(ns.cpu() if isinstance(ns, torch.Tensor) else ns)
+    return DeviceGathers(t(samples, torch.float32), t(sample_off, torch.int64),
+                         t(trace_ptr, torch.int32), t(ns, torch.int32),
+                         t(half_offset, torch.float32), t(midpoint, torch.float32),
+                         t(central_x, torch.float32), int(ns_host.max()) if ns_host.size else 1,
+                         float(np.float32(dt)))
+
+
+def upload_jobs(central, apert_ptr, apert_gather, out_off, n_out, device="cuda") -> DeviceJobs:
+    import torch
+
+    def t(a, dt_):
+        if a is None:
+            return None
+        return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt_)
+
+    ap = None if apert_ptr is None else np.asarray(apert_ptr)
+    max_apert = int(np.diff(ap).max()) if ap is not None and ap.size > 1 else 1
+    return DeviceJobs(t(central, torch.int32), t(apert_ptr, torch.int32),
+                      t(apert_gather, torch.int32), t(out_off, torch.int64), max(1, max_apert),
+                      int(n_out))
+
+
+# ---------------------------------------------------------------------------
+# the four calls
+# ---------------------------------------------------------------------------
+def _outputs(best, s_best, stack_out, panel) -> COutputs:
+    import torch
+    return COutputs(_typed(best, torch.int32, "best"), _typed(s_best, torch.float32, "s_best"),
+                    _typed(stack_out, torch.float32, "stack"), _typed(panel, torch.float32, "panel"))
+
+
+def cmp_scan(g: DeviceGathers, jobs: DeviceJobs, q, w: int, best, s_best, stack_out, ws,
+             panel=None, stream=None):
+    """Enqueue the CMP scan; results land in best / s_best / stack_out (/ panel)."""
+    import torch
+    gs, js, out = g.cstruct(), jobs.cstruct(), _outputs(best, s_best, stack_out, panel)
+    _check(lib().cmp_scan(C.byref(gs), C.byref(js), _typed(q, torch.float32, "q"), int(q.numel()),
+                          int(w), C.byref(out), _ptr(ws), int(ws.numel() * ws.element_size()),
+                          _stream(stream)))
+
+
+def crs_scan(g: DeviceGathers, jobs: DeviceJobs, A, B, q, w: int, best, s_best, stack_out, ws,
+             panel=None, stream=None):
+    """Enqueue the 2D CRS scan (flat parameter index (iA*nB + iB)*nq + iq)."""
+    import torch
+    gs, js, out = g.cstruct(), jobs.cstruct(), _outputs(best, s_best, stack_out, panel)
+    _check(lib().crs_scan(C.byref(gs), C.byref(js), _typed(A, torch.float32, "A"), int(A.numel()),
+                          _typed(B, torch.float32, "B"), int(B.numel()),
+                          _typed(q, torch.float32, "q"), int(q.numel()), int(w), C.byref(out),
+                          _ptr(ws), int(ws.numel() * ws.element_size()), _stream(stream)))
+
+
+def stack(g: DeviceGathers, jobs: DeviceJobs, kind: int, theta, w: int, s_out, stack_out, stream=None):
+    """Semblance and stack at theta[row] = (A, B, q) for every output row."""
+    import torch
+    gs, js = g.cstruct(), jobs.cstruct()
+    _check(lib().stack(C.byref(gs), C.byref(js), int(kind), _typed(theta, torch.float32, "theta"),
+                       int(w), _typed(s_out, torch.float32, "s_out"),
+                       _typed(stack_out, torch.float32, "stack_out"), _stream(stream)))
+
+
+def semblance_grad(g: DeviceGathers, jobs: DeviceJobs, kind: int, theta, g_s, w: int, g_theta,
+                   g_samples=None, stream=None):
+    """dL/dtheta (overwritten) and dL/dsamples (accumulated) for L = sum g_s * S."""
+    import torch
+    gs, js = g.cstruct(), jobs.cstruct()
+    _check(lib().semblance_grad(C.byref(gs), C.byref(js), int(kind),
+                                _typed(theta, torch.float32, "theta"),
+                                _typed(g_s, torch.float32, "g_s"), int(w),
+                                _typed(g_theta, torch.float32, "g_theta"),
+                                _typed(g_samples, torch.float32, "g_samples"), _stream(stream)))
+
+
+def alloc_workspace(nsamples: int, device="cuda"):
+    """A workspace tensor of the size cmp_scan / crs_scan need (256-byte aligned)."""
+    import torch
+    nbytes = workspace_bytes(nsamples)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]

@@ -1,0 +1,81 @@
+// internal.h -- declarations shared by the host API and the kernel
+// translation units of the semblance library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "semb.h"
+
+namespace semb {
+
+// Everything a scan kernel needs, passed by value as the kernel argument.
+struct ScanArgs {
+    // gathers
+    const float *samples;
+    const int64_t *sample_off;
+    const int32_t *trace_ptr;
+    const int32_t *ns;
+    const float *half_offset;
+    const float *midpoint;
+    const float *central_x;
+    float dt;
+    // jobs
+    const int32_t *central;
+    const int32_t *apert_ptr;    // NULL: aperture = {central}
+    const int32_t *apert_gather;
+    const int64_t *out_off;
+    int32_t njobs;
+    int32_t n_sblk;              // output-sample blocks per job (ceil(ns_max / 64))
+    // parameters; flat index = (iA * nB + iB) * nq + iq
+    const float *A;
+    const float *B;
+    const float *q;
+    int32_t nA, nB, nq, npar;
+    // outputs
+    int32_t *best;
+    float *s_best;
+    float *stack;
+    float *panel;
+    // window energy coefficients (workspace, FP64), one per sample
+    const double *c0;
+    const double *c1;
+    const double *c2;
+    int32_t w;
+};
+
+struct PointArgs {
+    const float *samples;
+    const int64_t *sample_off;
+    const int32_t *trace_ptr;
+    const int32_t *ns;
+    const float *half_offset;
+    const float *midpoint;
+    const float *central_x;
+    float dt;
+    const int32_t *central;
+    const int32_t *apert_ptr;
+    const int32_t *apert_gather;
+    const int64_t *out_off;
+    int32_t njobs;
+    int32_t n_sblk;
+    const float *theta;   // [n_out][3]
+    const float *g_s;     // [n_out] (gradient only)
+    float *s_out;
+    float *stack_out;
+    float *g_theta;       // [n_out][3]
+    float *g_samples;     // nullable
+    int32_t w;
+};
+
+// Launchers (return the hipError_t of the launch).
+hipError_t launch_energy_coeffs(const float *samples, const int64_t *sample_off,
+                                const int32_t *trace_ptr, const int32_t *ns, int32_t ngathers,
+                                int32_t ntraces, int32_t w, double *c0, double *c1, double *c2,
+                                hipStream_t stream);
+hipError_t launch_scan(int kind, const ScanArgs &a, hipStream_t stream);
+hipError_t launch_point(int kind, const PointArgs &a, hipStream_t stream);
+hipError_t launch_grad(int kind, const PointArgs &a, hipStream_t stream);
+
+}  // namespace semb

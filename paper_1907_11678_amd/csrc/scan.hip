@@ -1,0 +1,458 @@
+// scan.hip -- gfx950 kernels of the exhaustive CMP / 2D-CRS semblance scan.
+//
+// What is computed (Hu, Yang, Luan, Qian, "Massively Scaling Seismic
+// Processing on Sunway TaihuLight Supercomputer"): the grid search of
+// section 3.2 -- for every output sample t0 of a job and every candidate
+// parameter, the semblance of Eq. (1) over a w-sample window centred on each
+// trace's intersection with the traveltime curve (CMP, section 2.1) or
+// surface (CRS, section 2.2), each window sample linearly interpolated with
+// the intersection's fraction x (Algorithm 1); then the most coherent
+// parameter per sample and the stack along it.
+//
+// How it maps to CDNA4 (the paper's Sunway design is prior art, not copied):
+//   * one workgroup = (job, block of 64 consecutive output samples); lane l
+//     of every wave owns output sample s0 + l, and wave v owns P parameters of
+//     each parameter block.  All lanes of a wave therefore share the
+//     parameter and the trace, so the per-(parameter, trace) terms are
+//     wave-uniform values read from a small LDS table, and neighbouring lanes
+//     read neighbouring (or equal) LDS words -- no bank conflicts;
+//   * like the re-designed procedure of section 3.3.2 (Algorithm 2), traces
+//     are the outer loop and the per-pair sums U[w], D, M live in registers
+//     across all traces; for a chunk of traces the union [lo, hi] of the
+//     sample ranges the tile can touch (the paper's min_la..max_lb) is staged
+//     once into LDS with coalesced loads, which is also the paper's tiling of
+//     the merged intersections to fit local memory;
+//   * the window energy D_i = sum_j v_ij^2 is not accumulated sample by
+//     sample: with a shared fraction x it equals c0 + x (c1 + x c2), where
+//     c0, c1, c2 are sums over the raw window that depend only on the window
+//     start (energy_coeffs_kernel computes them once per sample).  The three
+//     terms can cancel (a window dominated by near-Nyquist content has a
+//     small interpolated energy but large c0), so they and D are kept in
+//     FP64, which CDNA4 executes at the FP32 rate.  U_j costs two FP32 FMAs
+//     per window sample, so a window costs 2w + 4 VALU operations instead of
+//     4w;
+//   * the fraction x is taken from d = tau - s = (T - s^2) / (sqrt(T) + s)
+//     (in samples), which has no cancellation, so x keeps ~1e-7 absolute
+//     accuracy in FP32 even at tau ~ 2000 samples;
+//   * the blockIdx -> tile map keeps consecutive tiles (one job) on one XCD so
+//     that the job's traces stay in that XCD's L2.
+//
+// Readings where the paper is silent are stated with the ABI in semb.h.
+
+#include "internal.h"
+
+namespace semb {
+namespace {
+
+constexpr int WAVE = 64;
+
+// The dispatcher deals workgroups round-robin over the 8 XCDs.  Map the k-th
+// workgroup of XCD x to a contiguous range of tiles so that the tiles of one
+// job share an L2.  A bijection of [0, nblk).
+__device__ __forceinline__ int xcd_tile(int bid, int nblk)
+{
+    const int per = nblk >> 3, rem = nblk & 7;
+    const int x = bid & 7, local = bid >> 3;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + local;
+}
+
+// ---------------------------------------------------------------------------
+// Window-energy coefficients: for window start n of a trace (n + w <= ns-1),
+//   c0 = sum_j f[n+j]^2, c1 = 2 sum_j f[n+j] (f[n+j+1]-f[n+j]),
+//   c2 = sum_j (f[n+j+1]-f[n+j])^2,             j = 0 .. w-1,
+// so that sum_j (f[n+j] + x (f[n+j+1]-f[n+j]))^2 = c0 + x c1 + x^2 c2.
+// Summed directly in FP64 (products of FP32 samples are exact there), one
+// block per trace.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+energy_coeffs_kernel(const float *__restrict__ samples, const int64_t *__restrict__ sample_off,
+                     const int32_t *__restrict__ trace_ptr, const int32_t *__restrict__ ns,
+                     int ngathers, int w, double *__restrict__ c0, double *__restrict__ c1,
+                     double *__restrict__ c2)
+{
+    const int t = blockIdx.x;
+    int lo = 0, hi = ngathers;  // largest g with trace_ptr[g] <= t
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (trace_ptr[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int n = ns[lo];
+    const int64_t base = sample_off[lo] + (int64_t)(t - trace_ptr[lo]) * n;
+    for (int p = threadIdx.x; p < n; p += blockDim.x) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        if (p + w <= n - 1) {
+            const float *f = samples + base + p;
+            double prev = f[0];
+            for (int j = 0; j < w; ++j) {
+                const double nxt = f[j + 1];
+                const double d = nxt - prev;  // exact: both are FP32 values
+                a0 = fma(prev, prev, a0);
+                a1 = fma(prev, d, a1);
+                a2 = fma(d, d, a2);
+                prev = nxt;
+            }
+            a1 *= 2.0;
+        }
+        c0[base + p] = a0;
+        c1[base + p] = a1;
+        c2[base + p] = a2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The scan.  KIND: SEMB_KIND_CMP / SEMB_KIND_CRS.  W: window.  P: parameters
+// per lane.  NW: waves per workgroup.  CAP: LDS sample positions per stage.
+// ---------------------------------------------------------------------------
+template <int KIND, int W, int P, int NW, int CAP>
+__global__ void __launch_bounds__(NW * WAVE)
+scan_kernel(ScanArgs a)
+{
+    constexpr int HW = (W - 1) / 2;
+    constexpr int NT = NW * P;  // parameters per block
+    constexpr int RMAX = WAVE;  // traces per stage (one per lane of wave 0)
+
+    __shared__ float lf[CAP];                 // staged samples
+    __shared__ double lc0[CAP], lc1[CAP], lc2[CAP];  // their energy coefficients
+    __shared__ float2 tab[NT][RMAX];          // per (parameter, trace) traveltime terms
+    __shared__ int2 tinfo[RMAX];              // (base - lo - HW, bits of ns - 2 - HW as float)
+    __shared__ long long t_src[RMAX];         // element of the trace's first staged sample
+    __shared__ int t_len[RMAX], t_base[RMAX];
+    __shared__ float t_h[RMAX], t_dm[RMAX];
+    __shared__ int ag_s[SEMB_APERT_LIMIT];
+    __shared__ int ag_cum[SEMB_APERT_LIMIT + 1];
+    __shared__ int sh_nfit;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
+
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int job = tile / a.n_sblk;
+    const int sblk = tile - job * a.n_sblk;
+    if (job >= a.njobs) return;
+    const int c = a.central[job];
+    const int nsc = a.ns[c];
+    const int s0 = sblk * WAVE;
+    if (s0 >= nsc) return;  // uniform over the workgroup, before any barrier
+    const int s1 = min(s0 + WAVE, nsc) - 1;
+    const int s = s0 + lane;
+    const bool lane_on = s < nsc;
+
+    // ---- the job's aperture: gathers and cumulative trace counts ----------
+    int na = 1, afirst = -1;
+    if (KIND == SEMB_KIND_CRS && a.apert_ptr != nullptr) {
+        afirst = a.apert_ptr[job];
+        na = min(a.apert_ptr[job + 1] - afirst, SEMB_APERT_LIMIT);
+        na = max(na, 0);
+    }
+    if (tid < na) ag_s[tid] = (afirst < 0) ? c : a.apert_gather[afirst + tid];
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        ag_cum[0] = 0;
+        for (int k = 0; k < na; ++k) {
+            const int g = ag_s[k];
+            acc += a.trace_ptr[g + 1] - a.trace_ptr[g];
+            ag_cum[k + 1] = acc;
+        }
+    }
+    __syncthreads();
+    const int ntr = ag_cum[na];
+    const double xc = (KIND == SEMB_KIND_CRS) ? (double)a.central_x[c] : 0.0;
+    const double inv_dt = 1.0 / (double)a.dt;
+
+    const float sf = (float)s;
+    const float s2 = sf * sf;
+    const float lo_lim = (float)(HW - s);  // window start >= 0  <=>  floor(d) >= HW - s
+
+    float bS = -1.f, bSt = 0.f;
+    int bI = 0;
+
+    for (int pb = 0; pb < a.npar; pb += NT) {
+        const int pe = min(pb + NT, a.npar);
+        // bounds of this block's parameters (wave-uniform)
+        double qlo = 1e300, qhi = -1e300, Alo = 1e300, Ahi = -1e300, Blo = 1e300, Bhi = -1e300;
+        for (int th = pb; th < pe; ++th) {
+            const int iq = th % a.nq;
+            const double qv = a.q[iq];
+            qlo = fmin(qlo, qv);
+            qhi = fmax(qhi, qv);
+            if (KIND == SEMB_KIND_CRS) {
+                const int iB = (th / a.nq) % a.nB, iA = th / (a.nq * a.nB);
+                Alo = fmin(Alo, (double)a.A[iA]);
+                Ahi = fmax(Ahi, (double)a.A[iA]);
+                Blo = fmin(Blo, (double)a.B[iB]);
+                Bhi = fmax(Bhi, (double)a.B[iB]);
+            }
+        }
+
+        float U[P][W], Mc[P];
+        double D[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) U[p][j] = 0.f;
+            D[p] = 0.0;
+            Mc[p] = 0.f;
+        }
+
+        for (int t0 = 0; t0 < ntr;) {
+            // ---- wave 0: sample range of the next traces, packed into LDS ----
+            if (wv == 0) {
+                const int t = t0 + lane;
+                int len = 0, lo = 0, nsg = 0;
+                long long src = 0;
+                float hh = 0.f, dmm = 0.f;
+                if (t < ntr) {
+                    int k = 0;
+                    while (k + 1 < na && ag_cum[k + 1] <= t) ++k;
+                    const int g = ag_s[k];
+                    const int li = t - ag_cum[k];
+                    const int i = a.trace_ptr[g] + li;
+                    nsg = a.ns[g];
+                    src = a.sample_off[g] + (long long)li * nsg;
+                    const double h = a.half_offset[i];
+                    const double cc = h * h * inv_dt * inv_dt;
+                    const double dm = (KIND == SEMB_KIND_CRS) ? (double)a.midpoint[i] - xc : 0.0;
+                    // bounds of T/dt^2 over the tile (interval arithmetic, FP64)
+                    double Tlo, Thi;
+                    const double gl = fmin(qlo * cc, qhi * cc), gh = fmax(qlo * cc, qhi * cc);
+                    if (KIND == SEMB_KIND_CMP) {
+                        Tlo = (double)s0 * s0 + gl;
+                        Thi = (double)s1 * s1 + gh;
+                    } else {
+                        const double ai = 2.0 * dm * inv_dt, bi = 2.0 * dm * dm * inv_dt;
+                        const double al = fmin(Alo * ai, Ahi * ai), ah = fmax(Alo * ai, Ahi * ai);
+                        const double bl = Blo * bi, bh = Bhi * bi;  // bi >= 0
+                        const double yl = s0 + al, yh = s1 + ah;
+                        const double y2l = yl > 0.0 ? yl * yl : (yh < 0.0 ? yh * yh : 0.0);
+                        const double y2h = fmax(yl * yl, yh * yh);
+                        const double sbl = fmin(fmin(s0 * bl, s0 * bh), fmin(s1 * bl, s1 * bh));
+                        const double sbh = fmax(fmax(s0 * bl, s0 * bh), fmax(s1 * bl, s1 * bh));
+                        Tlo = y2l + sbl + gl;
+                        Thi = y2h + sbh + gh;
+                    }
+                    if (Thi >= 0.0) {
+                        const long long klo = (long long)floor(sqrt(fmax(Tlo, 0.0))) - 1;
+                        const long long khi = (long long)floor(sqrt(Thi)) + 1;
+                        const long long l0 = max(0LL, klo - HW);
+                        const long long l1 = min((long long)nsg - 1, khi - HW + W);
+                        if (l1 >= l0) {
+                            lo = (int)l0;
+                            len = (int)(l1 - l0 + 1);
+                        }
+                    }
+                    hh = (float)h;
+                    dmm = (float)dm;
+                }
+                int incl = len;
+#pragma unroll
+                for (int o = 1; o < WAVE; o <<= 1) {
+                    const int v = __shfl_up(incl, o, WAVE);
+                    if (lane >= o) incl += v;
+                }
+                const bool fits = (t < ntr) && incl <= CAP;
+                const unsigned long long nf = __ballot(!fits);
+                int nfit = nf ? (__ffsll((long long)nf) - 1) : WAVE;
+                nfit = min(nfit, ntr - t0);
+                if (nfit == 0) {  // a single range larger than CAP: the host picks CAP >= ns_max
+                    nfit = 1;
+                    if (lane == 0) len = min(len, CAP), incl = len;
+                }
+                if (lane < nfit) {
+                    t_src[lane] = src + lo;
+                    t_len[lane] = len;
+                    t_base[lane] = incl - len;
+                    tinfo[lane] = make_int2(incl - len - lo - HW, __float_as_int((float)(nsg - 2 - HW)));
+                    t_h[lane] = hh;
+                    t_dm[lane] = dmm;
+                }
+                if (lane == 0) sh_nfit = nfit;
+            }
+            __syncthreads();
+            const int nfit = sh_nfit;
+
+            // ---- stage the samples and their coefficients (coalesced) -------
+            for (int r = wv; r < nfit; r += NW) {
+                const long long src = t_src[r];
+                const int len = t_len[r], base = t_base[r];
+                for (int p = lane; p < len; p += WAVE) {
+                    lf[base + p] = a.samples[src + p];
+                    lc0[base + p] = a.c0[src + p];
+                    lc1[base + p] = a.c1[src + p];
+                    lc2[base + p] = a.c2[src + p];
+                }
+            }
+            // ---- traveltime terms per (parameter, trace), rounded once from FP64
+            //   CMP: num = q h^2/dt^2
+            //   CRS: num = s (2 alpha + beta) + alpha^2 + gamma, with alpha = 2 A dm/dt,
+            //        beta = 2 B dm^2/dt, gamma = q h^2/dt^2; tab = (2 alpha + beta, alpha^2 + gamma)
+            for (int e = tid; e < NT * nfit; e += NW * WAVE) {
+                const int pl = e / nfit, r = e - pl * nfit;
+                const int th = pb + pl;
+                float2 v = make_float2(0.f, 0.f);
+                if (th < a.npar) {
+                    const double h = t_h[r];
+                    const double gam = (double)a.q[th % a.nq] * (h * h * inv_dt * inv_dt);
+                    if (KIND == SEMB_KIND_CMP) {
+                        v.x = (float)gam;
+                    } else {
+                        const int iB = (th / a.nq) % a.nB, iA = th / (a.nq * a.nB);
+                        const double dm = t_dm[r];
+                        const double al = (double)a.A[iA] * 2.0 * dm * inv_dt;
+                        const double be = (double)a.B[iB] * 2.0 * dm * dm * inv_dt;
+                        v.x = (float)(2.0 * al + be);
+                        v.y = (float)(al * al + gam);
+                    }
+                }
+                tab[pl][r] = v;
+            }
+            __syncthreads();
+
+            // ---- the hot loop: traces outer, this lane's P parameters inner ----
+            if (lane_on) {
+                for (int r = 0; r < nfit; ++r) {
+                    const int2 ti = tinfo[r];
+                    const int laneoff = s + ti.x;
+                    const float hilim = __int_as_float(ti.y) - sf;  // window end <= ns-1
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const float2 tv = tab[wv * P + p][r];
+                        const float num = (KIND == SEMB_KIND_CMP) ? tv.x : fmaf(sf, tv.x, tv.y);
+                        const float T = s2 + num;  // (tau)^2 in samples^2; NaN path if < 0
+                        const float rt = __builtin_amdgcn_sqrtf(T);
+                        const float d = num * __builtin_amdgcn_rcpf(rt + sf);  // tau - s
+                        const float kd = floorf(d);
+                        if (kd >= lo_lim && kd <= hilim) {
+                            const float x = d - kd;
+                            const float u = 1.f - x;
+                            const int idx = (int)kd + laneoff;
+                            float fw[W + 1];
+#pragma unroll
+                            for (int j = 0; j <= W; ++j) fw[j] = lf[idx + j];
+#pragma unroll
+                            for (int j = 0; j < W; ++j) {
+                                U[p][j] = fmaf(u, fw[j], U[p][j]);
+                                U[p][j] = fmaf(x, fw[j + 1], U[p][j]);
+                            }
+                            const double xd = x;
+                            D[p] += fma(xd, fma(xd, lc2[idx], lc1[idx]), lc0[idx]);
+                            Mc[p] += 1.f;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            t0 += nfit;
+        }
+
+        // ---- semblance of this block's parameters; running pick --------------
+        if (lane_on) {
+            const int64_t row = a.out_off[job] + s;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int th = pb + wv * P + p;
+                if (th < a.npar) {
+                    float N = 0.f, L = 0.f;
+#pragma unroll
+                    for (int j = 0; j < W; ++j) {
+                        N = fmaf(U[p][j], U[p][j], N);
+                        L += U[p][j];
+                    }
+                    const float MD = Mc[p] * (float)D[p];
+                    const float S = (Mc[p] > 0.f && D[p] > 0.0) ? N / MD : 0.f;
+                    const float st = (Mc[p] > 0.f) ? L / (Mc[p] * (float)W) : 0.f;
+                    if (a.panel) a.panel[row * a.npar + th] = S;
+                    if (S > bS) {  // parameters visited in increasing index: first max wins
+                        bS = S;
+                        bI = th;
+                        bSt = st;
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- pick across the waves (largest S, then smallest index) --------------
+    float *rS = lf;                                // reuse the stage buffers
+    int *rI = reinterpret_cast<int *>(lc0);
+    float *rT = reinterpret_cast<float *>(lc1);
+    __syncthreads();
+    rS[wv * WAVE + lane] = bS;
+    rI[wv * WAVE + lane] = bI;
+    rT[wv * WAVE + lane] = bSt;
+    __syncthreads();
+    if (wv == 0 && lane_on) {
+#pragma unroll
+        for (int v = 1; v < NW; ++v) {
+            const float S = rS[v * WAVE + lane];
+            const int I = rI[v * WAVE + lane];
+            if (S > bS || (S == bS && I < bI)) {
+                bS = S;
+                bI = I;
+                bSt = rT[v * WAVE + lane];
+            }
+        }
+        const int64_t row = a.out_off[job] + s;
+        a.best[row] = bI;
+        a.s_best[row] = bS < 0.f ? 0.f : bS;
+        a.stack[row] = bSt;
+    }
+}
+
+template <int KIND, int W>
+hipError_t launch_w(const ScanArgs &a, hipStream_t stream)
+{
+    constexpr int NW = 4;
+    const long long nblk = (long long)a.njobs * a.n_sblk;
+    if (nblk == 0) return hipSuccess;
+    constexpr int P = (W <= 15) ? 4 : 2;  // keeps the accumulators within ~160 VGPRs
+    hipLaunchKernelGGL((scan_kernel<KIND, W, P, NW, 2048>), dim3((unsigned)nblk), dim3(NW * WAVE), 0,
+                       stream, a);
+    return hipGetLastError();
+}
+
+template <int KIND>
+hipError_t launch_kind(const ScanArgs &a, hipStream_t stream)
+{
+    switch (a.w) {
+    case 1: return launch_w<KIND, 1>(a, stream);
+    case 3: return launch_w<KIND, 3>(a, stream);
+    case 5: return launch_w<KIND, 5>(a, stream);
+    case 7: return launch_w<KIND, 7>(a, stream);
+    case 9: return launch_w<KIND, 9>(a, stream);
+    case 11: return launch_w<KIND, 11>(a, stream);
+    case 13: return launch_w<KIND, 13>(a, stream);
+    case 15: return launch_w<KIND, 15>(a, stream);
+    case 17: return launch_w<KIND, 17>(a, stream);
+    case 19: return launch_w<KIND, 19>(a, stream);
+    case 21: return launch_w<KIND, 21>(a, stream);
+    case 23: return launch_w<KIND, 23>(a, stream);
+    case 25: return launch_w<KIND, 25>(a, stream);
+    case 27: return launch_w<KIND, 27>(a, stream);
+    case 29: return launch_w<KIND, 29>(a, stream);
+    case 31: return launch_w<KIND, 31>(a, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_energy_coeffs(const float *samples, const int64_t *sample_off,
+                                const int32_t *trace_ptr, const int32_t *ns, int32_t ngathers,
+                                int32_t ntraces, int32_t w, double *c0, double *c1, double *c2,
+                                hipStream_t stream)
+{
+    if (ntraces <= 0) return hipSuccess;
+    hipLaunchKernelGGL(energy_coeffs_kernel, dim3((unsigned)ntraces), dim3(256), 0, stream, samples,
+                       sample_off, trace_ptr, ns, ngathers, w, c0, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(int kind, const ScanArgs &a, hipStream_t stream)
+{
+    return kind == SEMB_KIND_CMP ? launch_kind<SEMB_KIND_CMP>(a, stream)
+                                 : launch_kind<SEMB_KIND_CRS>(a, stream);
+}
+
+}  // namespace semb

@@ -1,0 +1,85 @@
+"""Helpers for the GPU parity tests: run the HIP path through the C ABI on
+host-generated inputs and compare its outputs with the FP64 oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+# Tolerances ("parity"):
+S_TOL = 1e-5           # |S_gpu - S_oracle| on rows whose contributing set is not fragile
+PICK_GAP = 1e-4        # picks must be identical where best and runner-up differ by more
+STACK_TOL = 2e-5       # |stack_gpu - stack_oracle| relative to the row's sample scale
+
+
+def device_inputs(gs, jobs):
+    import paper_1907_11678_amd as semb
+    dg = semb.upload_gathers(gs.samples, gs.sample_off, gs.trace_ptr, gs.ns, gs.half_offset,
+                             gs.midpoint, gs.central_x, gs.dt)
+    dj = semb.upload_jobs(jobs.central, jobs.apert_ptr, jobs.apert_gather, jobs.out_off, jobs.n_out)
+    return dg, dj
+
+
+def run_scan(kind, gs, jobs, grid, w, panel=False, dg=None, dj=None):
+    import torch
+    import paper_1907_11678_amd as semb
+    if dg is None:
+        dg, dj = device_inputs(gs, jobs)
+    n = jobs.n_out
+    best = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+    sb = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+    st = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+    npar = grid.n if kind == "crs" else grid.q.size
+    pan = torch.full((n, npar), float("nan"), dtype=torch.float32, device="cuda") if panel else None
+    ws = semb.alloc_workspace(dg.nsamples)
+    q = torch.from_numpy(grid.q).cuda()
+    if kind == "cmp":
+        semb.cmp_scan(dg, dj, q, w, best, sb, st, ws, panel=pan)
+    else:
+        semb.crs_scan(dg, dj, torch.from_numpy(grid.A).cuda(), torch.from_numpy(grid.B).cuda(), q, w,
+                      best, sb, st, ws, panel=pan)
+    torch.cuda.synchronize()
+    return (best.cpu().numpy(), sb.cpu().numpy().astype(np.float64),
+            st.cpu().numpy().astype(np.float64),
+            None if pan is None else pan.cpu().numpy().astype(np.float64))
+
+
+def sample_scale(gs, jobs):
+    """Per output row: max |sample| over the job's aperture (stack tolerance scale)."""
+    out = np.zeros(jobs.n_out)
+    for j in range(jobs.njobs):
+        m = 0.0
+        for g in jobs.apert_gather[jobs.apert_ptr[j]:jobs.apert_ptr[j + 1]]:
+            gg = gs.gather(int(g))
+            if gg.size:
+                m = max(m, float(np.abs(gg).max()))
+        c = int(jobs.central[j])
+        out[jobs.out_off[j]:jobs.out_off[j] + int(gs.ns[c])] = m
+    return out
+
+
+def compare(name, gpu, ref, scale=None, rows=None):
+    """Assert parity of (best, s_best, stack[, panel]) against an oracle result.
+    rows: optional output-row indices the oracle result refers to."""
+    best, sb, st, pan = gpu
+    if rows is not None:
+        best, sb, st = best[rows], sb[rows], st[rows]
+        if scale is not None:
+            scale = scale[rows]
+    ok = ~ref.fragile
+    assert np.isfinite(sb).all() and (best >= 0).all(), f"{name}: unwritten outputs"
+    dS = np.abs(sb - ref.s_best)[ok]
+    worst = float(dS.max()) if dS.size else 0.0
+    assert worst <= S_TOL, f"{name}: max |dS| at the pick {worst:.3g} > {S_TOL}"
+    sure = ok & (ref.gap > PICK_GAP)
+    nbad = int((best[sure] != ref.best[sure]).sum())
+    assert nbad == 0, f"{name}: {nbad} of {int(sure.sum())} decisive picks differ"
+    same = ok & (best == ref.best)
+    sc = np.maximum(scale if scale is not None else 1.0, 1e-30)
+    dst = (np.abs(st - ref.stack) / sc)[same] if np.ndim(sc) else np.abs(st - ref.stack)[same] / sc
+    wst = float(dst.max()) if dst.size else 0.0
+    assert wst <= STACK_TOL, f"{name}: max relative |d stack| {wst:.3g} > {STACK_TOL}"
+    if pan is not None and ref.panel is not None:
+        dP = np.abs(pan - ref.panel)[ok]
+        assert np.isfinite(pan).all(), f"{name}: panel not fully written"
+        assert float(dP.max()) <= S_TOL, f"{name}: max |dS| over the panel {float(dP.max()):.3g}"
+    return {"rows": int(ref.s_best.size), "fragile": int((~ok).sum()), "max_dS": worst,
+            "decisive": int(sure.sum()), "max_dstack": wst}

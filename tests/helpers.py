@@ -108,14 +108,28 @@ def brute_scan(kind: str, gs, jobs, grid, w: int):
     return best, S[np.arange(S.shape[0]), best], ST[np.arange(S.shape[0]), best], S
 
 
+def seismic_like(rng: np.random.Generator, fold: int, ns: int, dt: float) -> np.ndarray:
+    """Band-limited random traces like the benchmark gathers: white noise
+    filtered by a Ricker wavelet of ~10 samples per period, plus white noise
+    at a third of its amplitude (an SNR of about 3)."""
+    f = 1.0 / (10.0 * dt)
+    k = np.arange(-25, 26)
+    wav = synth.ricker(k * dt, f)
+    x = rng.standard_normal((fold, ns + 50))
+    sig = np.stack([np.convolve(r, wav, mode="valid") for r in x])[:, :ns]
+    sig /= max(float(np.abs(sig).max()), 1e-30)
+    return sig + rng.standard_normal((fold, ns)) * (float(np.sqrt((sig ** 2).mean())) / 3.0)
+
+
 def random_line(rng: np.random.Generator, ngathers: int, fold_range=(1, 4), ns_range=(12, 40),
-                dt=0.004, hmax=300.0, spacing=12.5, zero_trace_prob=0.1):
-    """Tiny random gathers on a line (uneven fold and ns, some all-zero traces)."""
+                dt=0.004, hmax=300.0, spacing=12.5, zero_trace_prob=0.1, smooth=False):
+    """Tiny random gathers on a line (uneven fold and ns, some all-zero traces).
+    smooth=False: white Gaussian samples; smooth=True: seismic_like traces."""
     traces, hs, ms = [], [], []
     for g in range(ngathers):
         fold = int(rng.integers(fold_range[0], fold_range[1] + 1))
         ns = int(rng.integers(ns_range[0], ns_range[1] + 1))
-        t = rng.standard_normal((fold, ns)).astype(np.float32)
+        t = (seismic_like(rng, fold, ns, dt) if smooth else rng.standard_normal((fold, ns))).astype(np.float32)
         t[rng.random(fold) < zero_trace_prob] = 0.0
         traces.append(t)
         hs.append(np.sort(rng.uniform(0, hmax, fold)).astype(np.float32))

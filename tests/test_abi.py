@@ -1,0 +1,136 @@
+"""Host-side checks of the C ABI (no GPU needed, nothing is launched):
+the library loads, exports every function include/semb.h declares, and
+rejects invalid arguments before enqueueing anything."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "semb.h")
+
+
+@pytest.fixture(scope="module")
+def semb():
+    import paper_1907_11678_amd as pkg
+    if not os.path.exists(pkg.LIB_PATH):
+        from paper_1907_11678_amd import build
+        build.build()
+    pkg.lib()
+    return pkg
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_four_calls():
+    names = declared_functions()
+    for n in ("cmp_scan", "crs_scan", "stack", "semblance_grad", "semb_workspace_bytes",
+              "semb_last_error", "semb_version"):
+        assert n in names, names
+
+
+def test_library_exports_every_declared_function(semb):
+    out = subprocess.check_output(["nm", "-D", "--defined-only", semb.LIB_PATH]).decode()
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    L = C.CDLL(semb.LIB_PATH)
+    for n in declared_functions():
+        getattr(L, n)
+
+
+def test_library_targets_gfx950(semb):
+    blob = open(semb.LIB_PATH, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in blob
+
+
+def _gathers(semb, **kw):
+    fake = 0x1000  # never dereferenced: validation fails before any device access
+    g = semb.CGathers(fake, fake, fake, fake, fake, fake, fake, 1, 1, 64, 64, 0.004)
+    for k, v in kw.items():
+        setattr(g, k, v)
+    return g
+
+
+def _jobs(semb, **kw):
+    fake = 0x2000
+    j = semb.CJobs(fake, fake, fake, fake, 1, 1, 64)
+    for k, v in kw.items():
+        setattr(j, k, v)
+    return j
+
+
+def _outs(semb):
+    fake = 0x3000
+    return semb.COutputs(fake, fake, fake, None)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(g=dict(dt=0.0)), dict(g=dict(dt=float("nan"))), dict(g=dict(ns_max=0)),
+    dict(g=dict(ns_max=5000)), dict(g=dict(samples=None)), dict(g=dict(ngathers=0)),
+    dict(j=dict(njobs=-1)), dict(j=dict(max_apert=0)), dict(j=dict(central=None)),
+    dict(w=4), dict(w=0), dict(w=33), dict(nq=0),
+])
+def test_invalid_arguments_return_einval(semb, bad):
+    L = semb.lib()
+    g = _gathers(semb, **bad.get("g", {}))
+    j = _jobs(semb, **bad.get("j", {}))
+    out = _outs(semb)
+    st = L.cmp_scan(C.byref(g), C.byref(j), C.c_void_p(0x4000), bad.get("nq", 8), bad.get("w", 11),
+                    C.byref(out), C.c_void_p(0x10000), 1 << 20, None)
+    assert st == 1, semb.last_error()
+    assert semb.last_error()
+
+
+def test_crs_requires_midpoints_and_aperture(semb):
+    L = semb.lib()
+    g = _gathers(semb, midpoint=None)
+    j = _jobs(semb)
+    out = _outs(semb)
+    P = C.c_void_p(0x4000)
+    assert L.crs_scan(C.byref(g), C.byref(j), P, 2, P, 2, P, 2, 9, C.byref(out), C.c_void_p(0x10000),
+                      1 << 20, None) == 1
+    g = _gathers(semb)
+    j = _jobs(semb, apert_ptr=None)
+    assert L.crs_scan(C.byref(g), C.byref(j), P, 2, P, 2, P, 2, 9, C.byref(out), C.c_void_p(0x10000),
+                      1 << 20, None) == 1
+
+
+def test_small_or_misaligned_workspace(semb):
+    L = semb.lib()
+    g = _gathers(semb, nsamples=1000)
+    j = _jobs(semb)
+    out = _outs(semb)
+    need = semb.workspace_bytes(1000)
+    assert need >= 3 * 1000 * 8
+    P = C.c_void_p(0x4000)
+    assert L.cmp_scan(C.byref(g), C.byref(j), P, 8, 11, C.byref(out), C.c_void_p(0x10000), need - 1,
+                      None) == 2
+    assert L.cmp_scan(C.byref(g), C.byref(j), P, 8, 11, C.byref(out), C.c_void_p(0x10004), need,
+                      None) == 2
+    assert L.cmp_scan(C.byref(g), C.byref(j), P, 8, 11, C.byref(out), None, need, None) == 2
+
+
+def test_point_calls_validate(semb):
+    L = semb.lib()
+    g = _gathers(semb)
+    j = _jobs(semb)
+    P = C.c_void_p(0x4000)
+    assert L.stack(C.byref(g), C.byref(j), 7, P, 11, P, P, None) == 1          # bad kind
+    assert L.stack(C.byref(g), C.byref(j), 0, None, 11, P, P, None) == 1       # no theta
+    assert L.semblance_grad(C.byref(g), C.byref(j), 0, P, None, 11, P, None, None) == 1  # no g_s
+    assert L.semblance_grad(C.byref(g), C.byref(j), 1, P, P, 10, P, None, None) == 1    # even w
+
+
+def test_version(semb):
+    assert "gfx950" in semb.version()
