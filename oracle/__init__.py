@@ -52,6 +52,8 @@ class Library:
         for f in (L.oracle_scan, L.oracle_point, L.oracle_grad, L.oracle_scan_rows):
             f.restype = C.c_int
         L.oracle_max_threads.restype = C.c_int
+        L.oracle_set_fragility.argtypes = [C.c_double, C.c_double]
+        L.oracle_set_fragility.restype = None
         self.L = L
         self.path = path
 
@@ -77,6 +79,14 @@ def compile_variant(src_text: str, out_dir: str) -> Library:
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", so,
                            src, "-lm"])
     return Library(so)
+
+
+FRAGILE_DEFAULT = (1e-3, 1e-6)
+
+
+def set_fragility(tau_samples: float, t_rel: float, library: Library | None = None):
+    """Set the perturbations that flag a cell as fragile (see oracle.c)."""
+    (library or lib()).L.oracle_set_fragility(float(tau_samples), float(t_rel))
 
 
 def max_threads() -> int:

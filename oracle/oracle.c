@@ -60,9 +60,21 @@
 #define ORACLE_CRS 1
 
 /* Perturbations used to flag cells whose set of contributing traces could
- * differ between FP64 and FP32 arithmetic. */
-#define FRAGILE_TAU 1e-3    /* samples */
-#define FRAGILE_T_REL 1e-6  /* relative to the magnitude of T's terms */
+ * differ between this FP64 evaluation and another correct evaluation of the
+ * same definition in a different arithmetic: a trace is "near a boundary" if
+ * moving its intersection by FRAGILE_TAU samples, or its squared traveltime
+ * by FRAGILE_T_REL times the magnitude of its terms, changes whether it
+ * contributes.  The defaults suit an FP32 traveltime; a caller comparing with
+ * an implementation whose traveltime is exact to ~1e-10 samples can narrow
+ * them with oracle_set_fragility(). */
+static double FRAGILE_TAU = 1e-3;    /* samples */
+static double FRAGILE_T_REL = 1e-6;  /* relative */
+
+void oracle_set_fragility(double tau_samples, double t_rel)
+{
+    FRAGILE_TAU = tau_samples;
+    FRAGILE_T_REL = t_rel;
+}
 
 typedef struct {
     const float *samples;

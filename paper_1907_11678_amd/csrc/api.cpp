@@ -104,13 +104,13 @@ semb_status scan_common(int kind, const semb_gathers *g, const semb_jobs *jobs, 
         return fail(SEMB_EWORKSPACE, "workspace must be %zu bytes, 256-byte aligned (got %zu at %p)", need,
                     ws_bytes, ws);
 
-    const size_t plane = round_up((size_t)g->nsamples * sizeof(double));
-    double *c0 = static_cast<double *>(ws);
-    double *c1 = reinterpret_cast<double *>(static_cast<char *>(ws) + plane);
-    double *c2 = reinterpret_cast<double *>(static_cast<char *>(ws) + 2 * plane);
-    TRY(hip_status(semb::launch_energy_coeffs(g->samples, g->sample_off, g->trace_ptr, g->ns, g->ngathers,
-                                              g->ntraces, w, c0, c1, c2, stream),
-                   "energy coefficients launch"));
+    const size_t plane = round_up((size_t)g->nsamples * sizeof(float));
+    float *u0 = static_cast<float *>(ws);
+    float *u1 = reinterpret_cast<float *>(static_cast<char *>(ws) + plane);
+    float *u2sq = reinterpret_cast<float *>(static_cast<char *>(ws) + 2 * plane);
+    TRY(hip_status(semb::launch_window_energy(g->samples, g->sample_off, g->trace_ptr, g->ns, g->ngathers,
+                                              g->ntraces, w, u0, u1, u2sq, stream),
+                   "window energy launch"));
 
     semb::ScanArgs a{};
     a.samples = g->samples;
@@ -138,9 +138,9 @@ semb_status scan_common(int kind, const semb_gathers *g, const semb_jobs *jobs, 
     a.s_best = out->s_best;
     a.stack = out->stack;
     a.panel = out->panel;
-    a.c0 = c0;
-    a.c1 = c1;
-    a.c2 = c2;
+    a.u0 = u0;
+    a.u1 = u1;
+    a.u2sq = u2sq;
     a.w = w;
     return hip_status(semb::launch_scan(kind, a, stream), crs ? "crs_scan launch" : "cmp_scan launch");
 }
@@ -192,7 +192,7 @@ extern "C" {
 size_t semb_workspace_bytes(int64_t nsamples)
 {
     if (nsamples <= 0) return kAlign;
-    return 3 * round_up((size_t)nsamples * sizeof(double));
+    return 3 * round_up((size_t)nsamples * sizeof(float));
 }
 
 semb_status cmp_scan(const semb_gathers *g, const semb_jobs *jobs, const float *q, int32_t nq, int32_t w,

@@ -38,10 +38,10 @@ struct ScanArgs {
     float *s_best;
     float *stack;
     float *panel;
-    // window energy coefficients (workspace, FP64), one per sample
-    const double *c0;
-    const double *c1;
-    const double *c2;
+    // window energy in Gram form (workspace), one per sample
+    const float *u0;
+    const float *u1;
+    const float *u2sq;
     int32_t w;
 };
 
@@ -70,9 +70,9 @@ struct PointArgs {
 };
 
 // Launchers (return the hipError_t of the launch).
-hipError_t launch_energy_coeffs(const float *samples, const int64_t *sample_off,
+hipError_t launch_window_energy(const float *samples, const int64_t *sample_off,
                                 const int32_t *trace_ptr, const int32_t *ns, int32_t ngathers,
-                                int32_t ntraces, int32_t w, double *c0, double *c1, double *c2,
+                                int32_t ntraces, int32_t w, float *u0, float *u1, float *u2sq,
                                 hipStream_t stream);
 hipError_t launch_scan(int kind, const ScanArgs &a, hipStream_t stream);
 hipError_t launch_point(int kind, const PointArgs &a, hipStream_t stream);

@@ -6,10 +6,9 @@
 // but with a single parameter per output sample there is nothing to share
 // across parameters, so each lane owns one output sample and reads the trace
 // windows straight from global memory (neighbouring lanes read neighbouring
-// windows, which the L1/L2 caches coalesce).  The traveltime arithmetic --
-// terms rounded once from FP64, fraction from d = tau - s = (T - s^2) /
-// (sqrt(T) + s) -- is the scan's, so a point evaluation at a grid parameter
-// reproduces the scan's value.
+// windows, which the L1/L2 caches coalesce).  The intersection arithmetic
+// (FP64, traveltime.h) is the scan's, so a point evaluation at a grid
+// parameter reproduces the scan's value.
 //
 // Gradient (the ABI header states the formulas): pass 1 recomputes U, D, M
 // and S; pass 2 revisits every contributing trace, forms dS/dv for each
@@ -17,6 +16,7 @@
 // atomics (every output sample's windows overlap those of its neighbours).
 
 #include "internal.h"
+#include "traveltime.h"
 
 namespace semb {
 namespace {
@@ -30,8 +30,8 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk)
     return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + local;
 }
 
-// Traveltime of one (sample, trace) pair in the scan's arithmetic.
-struct Hit {
+// One (sample, trace) intersection in the scan's arithmetic (traveltime.h).
+struct Isect {
     bool valid;
     float x;      // fraction of the intersection
     int a;        // window start
@@ -39,29 +39,27 @@ struct Hit {
 };
 
 template <int KIND, int W>
-__device__ __forceinline__ Hit intersect(int s, double A, double B, double q, double h, double dm,
-                                         double inv_dt, int nsg)
+__device__ __forceinline__ Isect intersect(int s, double A, double B, double q, double h, double dm,
+                                           double inv_dt, int nsg)
 {
     constexpr int HW = (W - 1) / 2;
-    const double gam = q * (h * h * inv_dt * inv_dt);
-    const float sf = (float)s;
-    float num;
+    const double cc = h * h * inv_dt * inv_dt;
+    const double sd = (double)s;
+    double num;
     if (KIND == SEMB_KIND_CMP) {
-        num = (float)gam;
+        num = q * cc;
     } else {
         const double al = A * 2.0 * dm * inv_dt;
         const double be = B * 2.0 * dm * dm * inv_dt;
-        num = fmaf(sf, (float)(2.0 * al + be), (float)(al * al + gam));
+        num = fma(sd, 2.0 * al + be, fma(al, al, q * cc));
     }
-    const float T = fmaf(sf, sf, num);
-    const float rt = __builtin_amdgcn_sqrtf(T);
-    const float d = num * __builtin_amdgcn_rcpf(rt + sf);
-    const float kd = floorf(d);
-    Hit r;
-    r.valid = (kd >= (float)(HW - s)) && (kd <= (float)(nsg - 2 - HW - s));
-    r.x = d - kd;
-    r.a = r.valid ? (s + (int)kd - HW) : 0;
-    r.tau = sf + d;
+    const double T = sd * sd + num;
+    const Hit hit = hit_from_tau(sqrt_refined(T), HW);
+    Isect r;
+    r.valid = on_trace(hit.a, nsg - 1 - W) && (KIND == SEMB_KIND_CMP || T >= 0.0);
+    r.x = hit.x;
+    r.a = r.valid ? hit.a : 0;
+    r.tau = (float)hit.tau;
     return r;
 }
 
@@ -104,7 +102,7 @@ point_kernel(PointArgs a)
         for (int i = tb; i < te; ++i) {
             // displacement rounded to FP32 as the scan's trace table holds it
             const float dmf = (KIND == SEMB_KIND_CRS) ? (float)((double)a.midpoint[i] - xc) : 0.f;
-            const Hit hit = intersect<KIND, W>(s, A, B, q, a.half_offset[i], dmf, inv_dt, nsg);
+            const Isect hit = intersect<KIND, W>(s, A, B, q, a.half_offset[i], dmf, inv_dt, nsg);
             if (!hit.valid) continue;
             const float *f = a.samples + a.sample_off[g] + (int64_t)(i - tb) * nsg + hit.a;
             float prev = f[0];
@@ -148,7 +146,7 @@ point_kernel(PointArgs a)
             const int tb = a.trace_ptr[g], te = a.trace_ptr[g + 1];
             for (int i = tb; i < te; ++i) {
                 const float dmf = (KIND == SEMB_KIND_CRS) ? (float)((double)a.midpoint[i] - xc) : 0.f;
-                const Hit hit = intersect<KIND, W>(s, A, B, q, a.half_offset[i], dmf, inv_dt, nsg);
+                const Isect hit = intersect<KIND, W>(s, A, B, q, a.half_offset[i], dmf, inv_dt, nsg);
                 if (!hit.valid) continue;
                 const int64_t base = a.sample_off[g] + (int64_t)(i - tb) * nsg + hit.a;
                 const float *f = a.samples + base;

@@ -14,8 +14,8 @@
 //     of every wave owns output sample s0 + l, and wave v owns P parameters of
 //     each parameter block.  All lanes of a wave therefore share the
 //     parameter and the trace, so the per-(parameter, trace) terms are
-//     wave-uniform values read from a small LDS table, and neighbouring lanes
-//     read neighbouring (or equal) LDS words -- no bank conflicts;
+//     wave-uniform, and neighbouring lanes read neighbouring (or equal) LDS
+//     words -- no bank conflicts;
 //   * like the re-designed procedure of section 3.3.2 (Algorithm 2), traces
 //     are the outer loop and the per-pair sums U[w], D, M live in registers
 //     across all traces; for a chunk of traces the union [lo, hi] of the
@@ -23,23 +23,23 @@
 //     once into LDS with coalesced loads, which is also the paper's tiling of
 //     the merged intersections to fit local memory;
 //   * the window energy D_i = sum_j v_ij^2 is not accumulated sample by
-//     sample: with a shared fraction x it equals c0 + x (c1 + x c2), where
-//     c0, c1, c2 are sums over the raw window that depend only on the window
-//     start (energy_coeffs_kernel computes them once per sample).  The three
-//     terms can cancel (a window dominated by near-Nyquist content has a
-//     small interpolated energy but large c0), so they and D are kept in
-//     FP64, which CDNA4 executes at the FP32 rate.  U_j costs two FP32 FMAs
-//     per window sample, so a window costs 2w + 4 VALU operations instead of
-//     4w;
-//   * the fraction x is taken from d = tau - s = (T - s^2) / (sqrt(T) + s)
-//     (in samples), which has no cancellation, so x keeps ~1e-7 absolute
-//     accuracy in FP32 even at tau ~ 2000 samples;
+//     sample.  With the shared fraction x, v_ij = f[a+j] + x (f[a+j+1] -
+//     f[a+j]), so D_i is a quadratic in x whose coefficients depend only on
+//     the window start; window_energy_kernel writes it once per sample as a
+//     sum of two squares, D_i = (u0 + u1 x)^2 + u2^2 (Gram form of the two
+//     window vectors, computed in FP64), whose terms are never negative and so
+//     never cancel.  U_j costs two FMAs per window sample, so a window costs
+//     2w + 3 VALU operations and w + 4 LDS words;
+//   * the intersection is computed in FP64 (traveltime.h), so the set of
+//     contributing traces and the fraction x are those of an exact
+//     evaluation;
 //   * the blockIdx -> tile map keeps consecutive tiles (one job) on one XCD so
 //     that the job's traces stay in that XCD's L2.
 //
 // Readings where the paper is silent are stated with the ABI in semb.h.
 
 #include "internal.h"
+#include "traveltime.h"
 
 namespace semb {
 namespace {
@@ -57,18 +57,18 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk)
 }
 
 // ---------------------------------------------------------------------------
-// Window-energy coefficients: for window start n of a trace (n + w <= ns-1),
-//   c0 = sum_j f[n+j]^2, c1 = 2 sum_j f[n+j] (f[n+j+1]-f[n+j]),
-//   c2 = sum_j (f[n+j+1]-f[n+j])^2,             j = 0 .. w-1,
-// so that sum_j (f[n+j] + x (f[n+j+1]-f[n+j]))^2 = c0 + x c1 + x^2 c2.
-// Summed directly in FP64 (products of FP32 samples are exact there), one
-// block per trace.
+// Window energy in Gram form.  For window start n of a trace (n + w <= ns-1)
+// let a_j = f[n+j], b_j = f[n+j+1] - f[n+j] (j < w); the interpolated window
+// energy sum_j (a_j + x b_j)^2 = aa + 2 x ab + x^2 bb equals
+//   (u0 + u1 x)^2 + u2sq,  u1 = sqrt(bb), u0 = ab / u1, u2sq = aa - ab^2 / bb
+// (u1 = u0 = 0, u2sq = aa when bb = 0).  The sums are formed in FP64, where
+// products of FP32 samples are exact.  One block per trace.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
-energy_coeffs_kernel(const float *__restrict__ samples, const int64_t *__restrict__ sample_off,
+window_energy_kernel(const float *__restrict__ samples, const int64_t *__restrict__ sample_off,
                      const int32_t *__restrict__ trace_ptr, const int32_t *__restrict__ ns,
-                     int ngathers, int w, double *__restrict__ c0, double *__restrict__ c1,
-                     double *__restrict__ c2)
+                     int ngathers, int w, float *__restrict__ u0, float *__restrict__ u1,
+                     float *__restrict__ u2sq)
 {
     const int t = blockIdx.x;
     int lo = 0, hi = ngathers;  // largest g with trace_ptr[g] <= t
@@ -79,23 +79,31 @@ energy_coeffs_kernel(const float *__restrict__ samples, const int64_t *__restric
     const int n = ns[lo];
     const int64_t base = sample_off[lo] + (int64_t)(t - trace_ptr[lo]) * n;
     for (int p = threadIdx.x; p < n; p += blockDim.x) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        float r0 = 0.f, r1 = 0.f, r2 = 0.f;
         if (p + w <= n - 1) {
             const float *f = samples + base + p;
+            double aa = 0.0, ab = 0.0, bb = 0.0;
             double prev = f[0];
             for (int j = 0; j < w; ++j) {
                 const double nxt = f[j + 1];
                 const double d = nxt - prev;  // exact: both are FP32 values
-                a0 = fma(prev, prev, a0);
-                a1 = fma(prev, d, a1);
-                a2 = fma(d, d, a2);
+                aa = fma(prev, prev, aa);
+                ab = fma(prev, d, ab);
+                bb = fma(d, d, bb);
                 prev = nxt;
             }
-            a1 *= 2.0;
+            if (bb > 0.0) {
+                const double s1 = sqrt(bb);
+                r1 = (float)s1;
+                r0 = (float)(ab / s1);
+                r2 = (float)fmax(aa - ab * ab / bb, 0.0);
+            } else {
+                r2 = (float)aa;
+            }
         }
-        c0[base + p] = a0;
-        c1[base + p] = a1;
-        c2[base + p] = a2;
+        u0[base + p] = r0;
+        u1[base + p] = r1;
+        u2sq[base + p] = r2;
     }
 }
 
@@ -110,14 +118,16 @@ scan_kernel(ScanArgs a)
     constexpr int HW = (W - 1) / 2;
     constexpr int NT = NW * P;  // parameters per block
     constexpr int RMAX = WAVE;  // traces per stage (one per lane of wave 0)
+    constexpr bool CRS = KIND == SEMB_KIND_CRS;
 
-    __shared__ float lf[CAP];                 // staged samples
-    __shared__ double lc0[CAP], lc1[CAP], lc2[CAP];  // their energy coefficients
-    __shared__ float2 tab[NT][RMAX];          // per (parameter, trace) traveltime terms
-    __shared__ int2 tinfo[RMAX];              // (base - lo - HW, bits of ns - 2 - HW as float)
-    __shared__ long long t_src[RMAX];         // element of the trace's first staged sample
+    __shared__ float lf[CAP];                    // staged samples
+    __shared__ float lu0[CAP], lu1[CAP], lu2[CAP];  // their window energy (Gram form)
+    __shared__ double2 tab[CRS ? NT : 1][RMAX];  // CRS: (2 alpha + beta, alpha^2 + gamma)
+    __shared__ double t_cc[RMAX];                // h^2/dt^2 per staged trace
+    __shared__ int2 tinfo[RMAX];                 // (base - lo, ns - 1 - W)
+    __shared__ long long t_src[RMAX];            // element of the first staged sample
     __shared__ int t_len[RMAX], t_base[RMAX];
-    __shared__ float t_h[RMAX], t_dm[RMAX];
+    __shared__ float t_dm[RMAX];
     __shared__ int ag_s[SEMB_APERT_LIMIT];
     __shared__ int ag_cum[SEMB_APERT_LIMIT + 1];
     __shared__ int sh_nfit;
@@ -140,7 +150,7 @@ scan_kernel(ScanArgs a)
 
     // ---- the job's aperture: gathers and cumulative trace counts ----------
     int na = 1, afirst = -1;
-    if (KIND == SEMB_KIND_CRS && a.apert_ptr != nullptr) {
+    if (CRS && a.apert_ptr != nullptr) {
         afirst = a.apert_ptr[job];
         na = min(a.apert_ptr[job + 1] - afirst, SEMB_APERT_LIMIT);
         na = max(na, 0);
@@ -158,12 +168,11 @@ scan_kernel(ScanArgs a)
     }
     __syncthreads();
     const int ntr = ag_cum[na];
-    const double xc = (KIND == SEMB_KIND_CRS) ? (double)a.central_x[c] : 0.0;
+    const double xc = CRS ? (double)a.central_x[c] : 0.0;
     const double inv_dt = 1.0 / (double)a.dt;
 
-    const float sf = (float)s;
-    const float s2 = sf * sf;
-    const float lo_lim = (float)(HW - s);  // window start >= 0  <=>  floor(d) >= HW - s
+    const double sd = (double)s;
+    const double s2 = sd * sd;
 
     float bS = -1.f, bSt = 0.f;
     int bI = 0;
@@ -173,11 +182,10 @@ scan_kernel(ScanArgs a)
         // bounds of this block's parameters (wave-uniform)
         double qlo = 1e300, qhi = -1e300, Alo = 1e300, Ahi = -1e300, Blo = 1e300, Bhi = -1e300;
         for (int th = pb; th < pe; ++th) {
-            const int iq = th % a.nq;
-            const double qv = a.q[iq];
+            const double qv = a.q[th % a.nq];
             qlo = fmin(qlo, qv);
             qhi = fmax(qhi, qv);
-            if (KIND == SEMB_KIND_CRS) {
+            if (CRS) {
                 const int iB = (th / a.nq) % a.nB, iA = th / (a.nq * a.nB);
                 Alo = fmin(Alo, (double)a.A[iA]);
                 Ahi = fmax(Ahi, (double)a.A[iA]);
@@ -185,14 +193,20 @@ scan_kernel(ScanArgs a)
                 Bhi = fmax(Bhi, (double)a.B[iB]);
             }
         }
+        // this wave's own parameters (CMP: q as FP64; inactive slots get q = 0)
+        double qd[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int th = pb + wv * P + p;
+            qd[p] = (th < a.npar) ? (double)a.q[th % a.nq] : 0.0;
+        }
 
-        float U[P][W], Mc[P];
-        double D[P];
+        float U[P][W], D[P], Mc[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
 #pragma unroll
             for (int j = 0; j < W; ++j) U[p][j] = 0.f;
-            D[p] = 0.0;
+            D[p] = 0.f;
             Mc[p] = 0.f;
         }
 
@@ -202,7 +216,7 @@ scan_kernel(ScanArgs a)
                 const int t = t0 + lane;
                 int len = 0, lo = 0, nsg = 0;
                 long long src = 0;
-                float hh = 0.f, dmm = 0.f;
+                double cc = 0.0, dm = 0.0;
                 if (t < ntr) {
                     int k = 0;
                     while (k + 1 < na && ag_cum[k + 1] <= t) ++k;
@@ -212,12 +226,13 @@ scan_kernel(ScanArgs a)
                     nsg = a.ns[g];
                     src = a.sample_off[g] + (long long)li * nsg;
                     const double h = a.half_offset[i];
-                    const double cc = h * h * inv_dt * inv_dt;
-                    const double dm = (KIND == SEMB_KIND_CRS) ? (double)a.midpoint[i] - xc : 0.0;
-                    // bounds of T/dt^2 over the tile (interval arithmetic, FP64)
+                    cc = h * h * inv_dt * inv_dt;
+                    // the displacement as the kernels use it: rounded to FP32
+                    dm = CRS ? (double)(float)((double)a.midpoint[i] - xc) : 0.0;
+                    // bounds of tau^2 over the tile (interval arithmetic, FP64)
                     double Tlo, Thi;
                     const double gl = fmin(qlo * cc, qhi * cc), gh = fmax(qlo * cc, qhi * cc);
-                    if (KIND == SEMB_KIND_CMP) {
+                    if (!CRS) {
                         Tlo = (double)s0 * s0 + gl;
                         Thi = (double)s1 * s1 + gh;
                     } else {
@@ -233,6 +248,7 @@ scan_kernel(ScanArgs a)
                         Thi = y2h + sbh + gh;
                     }
                     if (Thi >= 0.0) {
+                        // one sample of margin on each side absorbs rounding
                         const long long klo = (long long)floor(sqrt(fmax(Tlo, 0.0))) - 1;
                         const long long khi = (long long)floor(sqrt(Thi)) + 1;
                         const long long l0 = max(0LL, klo - HW);
@@ -242,8 +258,6 @@ scan_kernel(ScanArgs a)
                             len = (int)(l1 - l0 + 1);
                         }
                     }
-                    hh = (float)h;
-                    dmm = (float)dm;
                 }
                 int incl = len;
 #pragma unroll
@@ -255,7 +269,7 @@ scan_kernel(ScanArgs a)
                 const unsigned long long nf = __ballot(!fits);
                 int nfit = nf ? (__ffsll((long long)nf) - 1) : WAVE;
                 nfit = min(nfit, ntr - t0);
-                if (nfit == 0) {  // a single range larger than CAP: the host picks CAP >= ns_max
+                if (nfit == 0) {  // a single range larger than CAP: the host keeps ns_max <= CAP
                     nfit = 1;
                     if (lane == 0) len = min(len, CAP), incl = len;
                 }
@@ -263,49 +277,44 @@ scan_kernel(ScanArgs a)
                     t_src[lane] = src + lo;
                     t_len[lane] = len;
                     t_base[lane] = incl - len;
-                    tinfo[lane] = make_int2(incl - len - lo - HW, __float_as_int((float)(nsg - 2 - HW)));
-                    t_h[lane] = hh;
-                    t_dm[lane] = dmm;
+                    // a trace without staged samples gets lim = -1: none of its windows count
+                    tinfo[lane] = make_int2(incl - len - lo, len > 0 ? nsg - 1 - W : -1);
+                    t_cc[lane] = cc;
+                    t_dm[lane] = (float)dm;
                 }
                 if (lane == 0) sh_nfit = nfit;
             }
             __syncthreads();
             const int nfit = sh_nfit;
 
-            // ---- stage the samples and their coefficients (coalesced) -------
+            // ---- stage the samples and their window energy (coalesced) ------
             for (int r = wv; r < nfit; r += NW) {
                 const long long src = t_src[r];
                 const int len = t_len[r], base = t_base[r];
                 for (int p = lane; p < len; p += WAVE) {
                     lf[base + p] = a.samples[src + p];
-                    lc0[base + p] = a.c0[src + p];
-                    lc1[base + p] = a.c1[src + p];
-                    lc2[base + p] = a.c2[src + p];
+                    lu0[base + p] = a.u0[src + p];
+                    lu1[base + p] = a.u1[src + p];
+                    lu2[base + p] = a.u2sq[src + p];
                 }
             }
-            // ---- traveltime terms per (parameter, trace), rounded once from FP64
-            //   CMP: num = q h^2/dt^2
-            //   CRS: num = s (2 alpha + beta) + alpha^2 + gamma, with alpha = 2 A dm/dt,
-            //        beta = 2 B dm^2/dt, gamma = q h^2/dt^2; tab = (2 alpha + beta, alpha^2 + gamma)
-            for (int e = tid; e < NT * nfit; e += NW * WAVE) {
-                const int pl = e / nfit, r = e - pl * nfit;
-                const int th = pb + pl;
-                float2 v = make_float2(0.f, 0.f);
-                if (th < a.npar) {
-                    const double h = t_h[r];
-                    const double gam = (double)a.q[th % a.nq] * (h * h * inv_dt * inv_dt);
-                    if (KIND == SEMB_KIND_CMP) {
-                        v.x = (float)gam;
-                    } else {
-                        const int iB = (th / a.nq) % a.nB, iA = th / (a.nq * a.nB);
-                        const double dm = t_dm[r];
-                        const double al = (double)a.A[iA] * 2.0 * dm * inv_dt;
-                        const double be = (double)a.B[iB] * 2.0 * dm * dm * inv_dt;
-                        v.x = (float)(2.0 * al + be);
-                        v.y = (float)(al * al + gam);
+            if (CRS) {
+                // per (parameter, trace): num = s u1 + u0 with
+                //   u1 = 2 alpha + beta, u0 = alpha^2 + gamma (FP64)
+                for (int e = tid; e < NT * nfit; e += NW * WAVE) {
+                    const int pl = e / nfit, r = e - pl * nfit;
+                    const int th = pb + pl;
+                    double2 v = make_double2(0.0, 0.0);
+                    if (th < a.npar) {
+                        const int iq = th % a.nq, iB = (th / a.nq) % a.nB, iA = th / (a.nq * a.nB);
+                        const double dmr = t_dm[r];
+                        const double al = (double)a.A[iA] * 2.0 * dmr * inv_dt;
+                        const double be = (double)a.B[iB] * 2.0 * dmr * dmr * inv_dt;
+                        v.x = 2.0 * al + be;
+                        v.y = fma(al, al, (double)a.q[iq] * t_cc[r]);
                     }
+                    tab[pl][r] = v;
                 }
-                tab[pl][r] = v;
             }
             __syncthreads();
 
@@ -313,20 +322,23 @@ scan_kernel(ScanArgs a)
             if (lane_on) {
                 for (int r = 0; r < nfit; ++r) {
                     const int2 ti = tinfo[r];
-                    const int laneoff = s + ti.x;
-                    const float hilim = __int_as_float(ti.y) - sf;  // window end <= ns-1
+                    if (ti.y < 0) continue;  // uniform
+                    const double cc = t_cc[r];
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        const float2 tv = tab[wv * P + p][r];
-                        const float num = (KIND == SEMB_KIND_CMP) ? tv.x : fmaf(sf, tv.x, tv.y);
-                        const float T = s2 + num;  // (tau)^2 in samples^2; NaN path if < 0
-                        const float rt = __builtin_amdgcn_sqrtf(T);
-                        const float d = num * __builtin_amdgcn_rcpf(rt + sf);  // tau - s
-                        const float kd = floorf(d);
-                        if (kd >= lo_lim && kd <= hilim) {
-                            const float x = d - kd;
+                        double num;
+                        if (CRS) {
+                            const double2 tv = tab[wv * P + p][r];
+                            num = fma(sd, tv.x, tv.y);
+                        } else {
+                            num = qd[p] * cc;
+                        }
+                        const double T = s2 + num;
+                        const Hit hit = hit_from_tau(sqrt_refined(T), HW);
+                        if (on_trace(hit.a, ti.y) && (!CRS || T >= 0.0)) {
+                            const float x = hit.x;
                             const float u = 1.f - x;
-                            const int idx = (int)kd + laneoff;
+                            const int idx = hit.a + ti.x;
                             float fw[W + 1];
 #pragma unroll
                             for (int j = 0; j <= W; ++j) fw[j] = lf[idx + j];
@@ -335,8 +347,8 @@ scan_kernel(ScanArgs a)
                                 U[p][j] = fmaf(u, fw[j], U[p][j]);
                                 U[p][j] = fmaf(x, fw[j + 1], U[p][j]);
                             }
-                            const double xd = x;
-                            D[p] += fma(xd, fma(xd, lc2[idx], lc1[idx]), lc0[idx]);
+                            const float tq = fmaf(x, lu1[idx], lu0[idx]);
+                            D[p] += fmaf(tq, tq, lu2[idx]);
                             Mc[p] += 1.f;
                         }
                     }
@@ -359,8 +371,7 @@ scan_kernel(ScanArgs a)
                         N = fmaf(U[p][j], U[p][j], N);
                         L += U[p][j];
                     }
-                    const float MD = Mc[p] * (float)D[p];
-                    const float S = (Mc[p] > 0.f && D[p] > 0.0) ? N / MD : 0.f;
+                    const float S = (Mc[p] > 0.f && D[p] > 0.f) ? N / (Mc[p] * D[p]) : 0.f;
                     const float st = (Mc[p] > 0.f) ? L / (Mc[p] * (float)W) : 0.f;
                     if (a.panel) a.panel[row * a.npar + th] = S;
                     if (S > bS) {  // parameters visited in increasing index: first max wins
@@ -374,9 +385,9 @@ scan_kernel(ScanArgs a)
     }
 
     // ---- pick across the waves (largest S, then smallest index) --------------
-    float *rS = lf;                                // reuse the stage buffers
-    int *rI = reinterpret_cast<int *>(lc0);
-    float *rT = reinterpret_cast<float *>(lc1);
+    float *rS = lf;  // reuse the stage buffers
+    int *rI = reinterpret_cast<int *>(lu0);
+    float *rT = lu1;
     __syncthreads();
     rS[wv * WAVE + lane] = bS;
     rI[wv * WAVE + lane] = bI;
@@ -438,14 +449,14 @@ hipError_t launch_kind(const ScanArgs &a, hipStream_t stream)
 
 }  // namespace
 
-hipError_t launch_energy_coeffs(const float *samples, const int64_t *sample_off,
+hipError_t launch_window_energy(const float *samples, const int64_t *sample_off,
                                 const int32_t *trace_ptr, const int32_t *ns, int32_t ngathers,
-                                int32_t ntraces, int32_t w, double *c0, double *c1, double *c2,
+                                int32_t ntraces, int32_t w, float *u0, float *u1, float *u2sq,
                                 hipStream_t stream)
 {
     if (ntraces <= 0) return hipSuccess;
-    hipLaunchKernelGGL(energy_coeffs_kernel, dim3((unsigned)ntraces), dim3(256), 0, stream, samples,
-                       sample_off, trace_ptr, ns, ngathers, w, c0, c1, c2);
+    hipLaunchKernelGGL(window_energy_kernel, dim3((unsigned)ntraces), dim3(256), 0, stream, samples,
+                       sample_off, trace_ptr, ns, ngathers, w, u0, u1, u2sq);
     return hipGetLastError();
 }
 

@@ -112,7 +112,7 @@ def test_small_or_misaligned_workspace(semb):
     j = _jobs(semb)
     out = _outs(semb)
     need = semb.workspace_bytes(1000)
-    assert need >= 3 * 1000 * 8
+    assert need >= 3 * 1000 * 4
     P = C.c_void_p(0x4000)
     assert L.cmp_scan(C.byref(g), C.byref(j), P, 8, 11, C.byref(out), C.c_void_p(0x10000), need - 1,
                       None) == 2
