@@ -56,7 +56,7 @@ __device__ __forceinline__ Isect intersect(int s, double A, double B, double q, 
     const double T = sd * sd + num;
     const Hit hit = hit_from_tau(sqrt_refined(T), HW);
     Isect r;
-    r.valid = on_trace(hit.a, nsg - 1 - W) && (KIND == SEMB_KIND_CMP || T >= 0.0);
+    r.valid = on_trace(hit.a, nsg - 1 - W) && T >= 0.0;
     r.x = hit.x;
     r.a = r.valid ? hit.a : 0;
     r.tau = (float)hit.tau;

@@ -46,6 +46,37 @@ namespace {
 
 constexpr int WAVE = 64;
 
+typedef __attribute__((address_space(3))) void lds_void;
+
+// One dword per lane from global memory straight into LDS: lane l writes LDS
+// word (lds_base + l); lds_base must be the same for the whole wave.
+__device__ __forceinline__ void lds_dma(const float *g, float *lds_base)
+{
+    __builtin_amdgcn_global_load_lds((void *)g, (lds_void *)lds_base, 4, 0, 0);
+}
+
+// A wave-uniform double moved into scalar registers (frees two VGPRs).
+__device__ __forceinline__ double to_sgpr(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 // The dispatcher deals workgroups round-robin over the 8 XCDs.  Map the k-th
 // workgroup of XCD x to a contiguous range of tiles so that the tiles of one
 // job share an L2.  A bijection of [0, nblk).
@@ -111,8 +142,9 @@ window_energy_kernel(const float *__restrict__ samples, const int64_t *__restric
 // The scan.  KIND: SEMB_KIND_CMP / SEMB_KIND_CRS.  W: window.  P: parameters
 // per lane.  NW: waves per workgroup.  CAP: LDS sample positions per stage.
 // ---------------------------------------------------------------------------
-template <int KIND, int W, int P, int NW, int CAP>
-__global__ void __launch_bounds__(NW * WAVE)
+// WPE: minimum waves per SIMD the register allocation must allow.
+template <int KIND, int W, int P, int NW, int CAP, int WPE>
+__global__ void __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(WPE)))
 scan_kernel(ScanArgs a)
 {
     constexpr int HW = (W - 1) / 2;
@@ -128,6 +160,7 @@ scan_kernel(ScanArgs a)
     __shared__ long long t_src[RMAX];            // element of the first staged sample
     __shared__ int t_len[RMAX], t_base[RMAX];
     __shared__ float t_dm[RMAX];
+    __shared__ double pq[NT], pA[NT], pB[NT];    // this block's parameters
     __shared__ int ag_s[SEMB_APERT_LIMIT];
     __shared__ int ag_cum[SEMB_APERT_LIMIT + 1];
     __shared__ int sh_nfit;
@@ -180,25 +213,36 @@ scan_kernel(ScanArgs a)
     for (int pb = 0; pb < a.npar; pb += NT) {
         const int pe = min(pb + NT, a.npar);
         // bounds of this block's parameters (wave-uniform)
-        double qlo = 1e300, qhi = -1e300, Alo = 1e300, Ahi = -1e300, Blo = 1e300, Bhi = -1e300;
-        for (int th = pb; th < pe; ++th) {
-            const double qv = a.q[th % a.nq];
-            qlo = fmin(qlo, qv);
-            qhi = fmax(qhi, qv);
-            if (CRS) {
-                const int iB = (th / a.nq) % a.nB, iA = th / (a.nq * a.nB);
-                Alo = fmin(Alo, (double)a.A[iA]);
-                Ahi = fmax(Ahi, (double)a.A[iA]);
-                Blo = fmin(Blo, (double)a.B[iB]);
-                Bhi = fmax(Bhi, (double)a.B[iB]);
+        // ---- this block's parameters, decoded once by wave 0 (one per lane) into
+        // LDS, with their bounds reduced across the wave.  The previous block
+        // ended with a barrier, so the parameter arrays are free.
+        double qlo = 0.0, qhi = 0.0, Alo = 0.0, Ahi = 0.0, Blo = 0.0, Bhi = 0.0;
+        if (wv == 0) {
+            const int th = pb + lane;
+            const bool on = lane < NT && th < a.npar;
+            double qv = 0.0, Av = 0.0, Bv = 0.0;
+            if (on) {
+                const int iq = th % a.nq;
+                qv = a.q[iq];
+                if (CRS) {
+                    const int rest = th / a.nq;
+                    Bv = a.B[rest % a.nB];
+                    Av = a.A[rest / a.nB];
+                }
             }
-        }
-        // this wave's own parameters (CMP: q as FP64; inactive slots get q = 0)
-        double qd[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const int th = pb + wv * P + p;
-            qd[p] = (th < a.npar) ? (double)a.q[th % a.nq] : 0.0;
+            if (lane < NT) {
+                pq[lane] = qv;
+                pA[lane] = Av;
+                pB[lane] = Bv;
+            }
+            qlo = wave_min(on ? qv : 1e300);
+            qhi = wave_max(on ? qv : -1e300);
+            if (CRS) {
+                Alo = wave_min(on ? Av : 1e300);
+                Ahi = wave_max(on ? Av : -1e300);
+                Blo = wave_min(on ? Bv : 1e300);
+                Bhi = wave_max(on ? Bv : -1e300);
+            }
         }
 
         float U[P][W], D[P], Mc[P];
@@ -249,8 +293,8 @@ scan_kernel(ScanArgs a)
                     }
                     if (Thi >= 0.0) {
                         // one sample of margin on each side absorbs rounding
-                        const long long klo = (long long)floor(sqrt(fmax(Tlo, 0.0))) - 1;
-                        const long long khi = (long long)floor(sqrt(Thi)) + 1;
+                        const long long klo = (long long)floor(sqrt_refined(Tlo)) - 1;
+                        const long long khi = (long long)floor(sqrt_refined(Thi)) + 1;
                         const long long l0 = max(0LL, klo - HW);
                         const long long l1 = min((long long)nsg - 1, khi - HW + W);
                         if (l1 >= l0) {
@@ -287,43 +331,53 @@ scan_kernel(ScanArgs a)
             __syncthreads();
             const int nfit = sh_nfit;
 
-            // ---- stage the samples and their window energy (coalesced) ------
+            // ---- stage the samples and their window energy -------------------
+            // Direct global->LDS loads (global_load_lds_dword): lane l of a wave
+            // fetches element p0 + l of the trace's range into LDS word
+            // base + p0 + l without passing through registers, so every load of
+            // the chunk is in flight at once; the barrier below waits for them.
             for (int r = wv; r < nfit; r += NW) {
                 const long long src = t_src[r];
                 const int len = t_len[r], base = t_base[r];
-                for (int p = lane; p < len; p += WAVE) {
-                    lf[base + p] = a.samples[src + p];
-                    lu0[base + p] = a.u0[src + p];
-                    lu1[base + p] = a.u1[src + p];
-                    lu2[base + p] = a.u2sq[src + p];
+                for (int p0 = 0; p0 < len; p0 += WAVE) {
+                    if (p0 + lane < len) {
+                        const long long gi = src + p0 + lane;
+                        lds_dma(a.samples + gi, &lf[base + p0]);
+                        lds_dma(a.u0 + gi, &lu0[base + p0]);
+                        lds_dma(a.u1 + gi, &lu1[base + p0]);
+                        lds_dma(a.u2sq + gi, &lu2[base + p0]);
+                    }
                 }
             }
             if (CRS) {
                 // per (parameter, trace): num = s u1 + u0 with
                 //   u1 = 2 alpha + beta, u0 = alpha^2 + gamma (FP64)
-                for (int e = tid; e < NT * nfit; e += NW * WAVE) {
-                    const int pl = e / nfit, r = e - pl * nfit;
-                    const int th = pb + pl;
-                    double2 v = make_double2(0.0, 0.0);
-                    if (th < a.npar) {
-                        const int iq = th % a.nq, iB = (th / a.nq) % a.nB, iA = th / (a.nq * a.nB);
-                        const double dmr = t_dm[r];
-                        const double al = (double)a.A[iA] * 2.0 * dmr * inv_dt;
-                        const double be = (double)a.B[iB] * 2.0 * dmr * dmr * inv_dt;
-                        v.x = 2.0 * al + be;
-                        v.y = fma(al, al, (double)a.q[iq] * t_cc[r]);
+                for (int pl = wv; pl < NT; pl += NW) {
+                    if (lane < nfit) {
+                        const double dmr = t_dm[lane];
+                        const double al = pA[pl] * 2.0 * dmr * inv_dt;
+                        const double be = pB[pl] * 2.0 * dmr * dmr * inv_dt;
+                        tab[pl][lane] = make_double2(2.0 * al + be, fma(al, al, pq[pl] * t_cc[lane]));
                     }
-                    tab[pl][r] = v;
                 }
             }
             __syncthreads();
 
             // ---- the hot loop: traces outer, this lane's P parameters inner ----
+            // First the P intersections (independent FP64 chains), then the P
+            // windows without branches: a window that is off the trace reads a
+            // harmless in-range LDS word with zero weights, so the loads of all
+            // P windows can be in flight together.
+            double qd[P];  // this wave's parameters (CMP), held in scalar registers
+#pragma unroll
+            for (int p = 0; p < P; ++p) qd[p] = to_sgpr(pq[wv * P + p]);
             if (lane_on) {
                 for (int r = 0; r < nfit; ++r) {
                     const int2 ti = tinfo[r];
-                    if (ti.y < 0) continue;  // uniform
+                    if (ti.y < 0) continue;  // uniform: no staged window on this trace
                     const double cc = t_cc[r];
+                    int idx[P];
+                    float xw[P], uw[P], vm[P];
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         double num;
@@ -335,22 +389,26 @@ scan_kernel(ScanArgs a)
                         }
                         const double T = s2 + num;
                         const Hit hit = hit_from_tau(sqrt_refined(T), HW);
-                        if (on_trace(hit.a, ti.y) && (!CRS || T >= 0.0)) {
-                            const float x = hit.x;
-                            const float u = 1.f - x;
-                            const int idx = hit.a + ti.x;
-                            float fw[W + 1];
+                        const bool ok = on_trace(hit.a, ti.y) && T >= 0.0;
+                        idx[p] = ok ? hit.a + ti.x : 0;
+                        xw[p] = ok ? hit.x : 0.f;
+                        vm[p] = ok ? 1.f : 0.f;
+                        uw[p] = vm[p] - xw[p];
+                    }
 #pragma unroll
-                            for (int j = 0; j <= W; ++j) fw[j] = lf[idx + j];
+                    for (int p = 0; p < P; ++p) {
+                        const int id = idx[p];
+                        float fw[W + 1];
 #pragma unroll
-                            for (int j = 0; j < W; ++j) {
-                                U[p][j] = fmaf(u, fw[j], U[p][j]);
-                                U[p][j] = fmaf(x, fw[j + 1], U[p][j]);
-                            }
-                            const float tq = fmaf(x, lu1[idx], lu0[idx]);
-                            D[p] += fmaf(tq, tq, lu2[idx]);
-                            Mc[p] += 1.f;
+                        for (int j = 0; j <= W; ++j) fw[j] = lf[id + j];
+#pragma unroll
+                        for (int j = 0; j < W; ++j) {
+                            U[p][j] = fmaf(uw[p], fw[j], U[p][j]);
+                            U[p][j] = fmaf(xw[p], fw[j + 1], U[p][j]);
                         }
+                        const float tq = fmaf(xw[p], lu1[id], lu0[id]);
+                        D[p] = fmaf(vm[p], fmaf(tq, tq, lu2[id]), D[p]);
+                        Mc[p] += vm[p];
                     }
                 }
             }
@@ -411,14 +469,22 @@ scan_kernel(ScanArgs a)
     }
 }
 
+// Tile shape per kind (measured on MI355X, see the design notes): CMP keeps 4
+// parameters per lane in 4 waves at <= 128 VGPRs (4 waves per SIMD); CRS, whose
+// per-eval table read and larger apertures favour occupancy, uses 2
+// parameters per lane in 8 waves.  Stage capacity: 2048 positions (CMP, four
+// workgroups per CU), 3072 (CRS, two workgroups per CU).
 template <int KIND, int W>
 hipError_t launch_w(const ScanArgs &a, hipStream_t stream)
 {
-    constexpr int NW = 4;
+    constexpr bool CRS = KIND == SEMB_KIND_CRS;
+    constexpr int NW = CRS ? 8 : 4;
+    constexpr int P = CRS ? 2 : (W <= 15 ? 4 : 2);
+    constexpr int WPE = CRS ? 1 : 4;
+    constexpr int CAP = CRS ? 3072 : 2048;
     const long long nblk = (long long)a.njobs * a.n_sblk;
     if (nblk == 0) return hipSuccess;
-    constexpr int P = (W <= 15) ? 4 : 2;  // keeps the accumulators within ~160 VGPRs
-    hipLaunchKernelGGL((scan_kernel<KIND, W, P, NW, 2048>), dim3((unsigned)nblk), dim3(NW * WAVE), 0,
+    hipLaunchKernelGGL((scan_kernel<KIND, W, P, NW, CAP, WPE>), dim3((unsigned)nblk), dim3(NW * WAVE), 0,
                        stream, a);
     return hipGetLastError();
 }

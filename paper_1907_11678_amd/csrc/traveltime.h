@@ -18,17 +18,18 @@
 
 namespace semb {
 
-// tau = sqrt(max(T, 0)); 0 for T <= 0 (callers test T < 0 themselves).
+// tau = sqrt(max(T, 1e-300)): the square root for T > 0 and ~1e-150 (floor 0,
+// fraction 0 in FP32) for T <= 0; callers reject T < 0 themselves.
 __device__ __forceinline__ double sqrt_refined(double T)
 {
-    const double Tc = fmax(T, 0.0);
-    const double y = __builtin_amdgcn_rsq(fmax(Tc, 1e-300));  // ~1/sqrt(T), rel. err ~2^-23
-    const double t0 = Tc * y;
-    const double r = fma(-t0, t0, Tc);
+    const double Tm = fmax(T, 1e-300);
+    const double y = __builtin_amdgcn_rsq(Tm);  // ~1/sqrt(T), rel. err ~2^-23
+    const double t0 = Tm * y;
+    const double r = fma(-t0, t0, Tm);
     return fma(r, 0.5 * y, t0);
 }
 
-// Window start a = floor(tau) - hw and fraction x of one intersection.
+// Window start a = floor(tau) - hw and fraction x of one intersection, tau >= 0.
 struct Hit {
     int a;
     float x;
@@ -37,10 +38,13 @@ struct Hit {
 
 __device__ __forceinline__ Hit hit_from_tau(double tau, int hw)
 {
-    const double kf = fmin(floor(tau), 1073741824.0);  // tau >= 0; keeps the conversion in range
+    // a tau of 2^30 or more cannot start a window on any trace the ABI accepts;
+    // the clamp keeps the conversion in range, where truncation is floor
+    const double tc = fmin(tau, 1073741824.0);
+    const int k = (int)tc;
     Hit h;
-    h.a = (int)kf - hw;
-    h.x = (float)(tau - kf);
+    h.a = k - hw;
+    h.x = (float)(tc - (double)k);
     h.tau = tau;
     return h;
 }
