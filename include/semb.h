@@ -160,6 +160,80 @@ semb_status semblance_grad(const semb_gathers *g, const semb_jobs *jobs, int32_t
                            const float *theta, const float *g_s, int32_t w, float *g_theta,
                            float *g_samples, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched scan: CMP and CRS jobs of uneven fold and length in ONE persistent
+ * launch (the paper processes CDPs as independent tasks, section 3.5; here
+ * they are balanced across the GPU instead of across core groups).
+ *
+ * Work is cut into tiles = (job, block of 64 output samples, range of flat
+ * parameter indices).  semb_batch_plan builds the tile list on the host,
+ * longest first by estimated cost (samples x parameters x traces); tiles of
+ * one (job, sample block) that split its parameter range form a group whose
+ * partial picks the last-finishing tile merges.  scan_batch runs the list:
+ * workgroups take tiles from an atomic counter until none is left.
+ * ------------------------------------------------------------------------- */
+typedef struct semb_tile {
+    int32_t job;        /* job index                                             */
+    int32_t sblk;       /* output samples 64*sblk .. 64*sblk+63 of the job       */
+    int32_t p_begin;    /* flat parameter indices p_begin .. p_end-1             */
+    int32_t p_end;
+    int32_t group;      /* group id (tiles of one job/sample block), -1 if alone */
+    int32_t split;      /* position within the group                             */
+    int32_t nsplit;     /* tiles in the group (1 if alone)                       */
+    int32_t part_base;  /* first partial slot of the group                       */
+} semb_tile;
+
+/* Host description of a batch, for planning.  [host] arrays. */
+typedef struct semb_batch_host {
+    int32_t njobs;
+    const int32_t *kind;          /* [njobs] SEMB_KIND_CMP or SEMB_KIND_CRS          */
+    const int32_t *central;       /* [njobs]                                         */
+    const int32_t *apert_ptr;     /* [njobs + 1] aperture CSR (CMP jobs may list only
+                                     the central gather; their aperture is ignored)  */
+    const int32_t *apert_gather;
+    int32_t ngathers;
+    const int32_t *ns;            /* [ngathers]                                      */
+    const int32_t *trace_ptr;     /* [ngathers + 1]                                  */
+    int32_t npar_cmp;             /* parameters of a CMP job                         */
+    int32_t npar_crs;             /* parameters of a CRS job                         */
+} semb_batch_host;
+
+/* Build the tile list (at most split_params parameters per tile, rounded up to
+ * a multiple of 16).  tiles may be NULL to query the count.  On success
+ * returns the number of tiles and sets *ngroups and *nparts (partial slots);
+ * returns -1 (see semb_last_error) on invalid input or if max_tiles is too
+ * small.  [host] */
+int64_t semb_batch_plan(const semb_batch_host *h, int32_t split_params, semb_tile *tiles,
+                        int64_t max_tiles, int32_t *ngroups, int32_t *nparts);
+
+/* Device-side parameters of a batch. */
+typedef struct semb_batch {
+    const int32_t *kind;          /* [njobs] device                                  */
+    const float *q_cmp;           /* CMP grid [nq_cmp]                               */
+    int32_t nq_cmp;
+    int32_t w_cmp;                /* CMP window: 9, 11 or 15                         */
+    const float *A;               /* CRS grid, flat (iA * nB + iB) * nq_crs + iq     */
+    int32_t nA;
+    const float *B;
+    int32_t nB;
+    const float *q_crs;
+    int32_t nq_crs;
+    int32_t w_crs;                /* CRS window: 9, 11 or 15                         */
+} semb_batch;
+
+/* Workspace for scan_batch. [host] */
+size_t semb_batch_workspace_bytes(int64_t nsamples, int32_t w_cmp, int32_t w_crs, int32_t ngroups,
+                                  int32_t nparts);
+
+/* Run a planned batch (tiles: device copy of the plan).  Outputs as for the
+ * scans (panel must be NULL); best indexes the job's own grid.  The workspace
+ * holds the window-energy planes, the tile and group counters (reset by a
+ * kernel on `stream`, so the call can be captured in a HIP graph and
+ * replayed) and the partial picks.  Calls that overlap on one workspace race. */
+semb_status scan_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_batch *b,
+                       const semb_tile *tiles, int64_t ntiles, int32_t ngroups, int32_t nparts,
+                       const semb_outputs *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Message describing the last non-OK status returned on this thread. [host] */
 const char *semb_last_error(void);
 

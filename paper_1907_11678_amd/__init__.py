@@ -53,6 +53,24 @@ class COutputs(C.Structure):
                 ("panel", C.c_void_p)]
 
 
+class CTile(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("job", "sblk", "p_begin", "p_end", "group", "split", "nsplit",
+                                          "part_base")]
+
+
+class CBatchHost(C.Structure):
+    _fields_ = [("njobs", C.c_int32), ("kind", C.c_void_p), ("central", C.c_void_p),
+                ("apert_ptr", C.c_void_p), ("apert_gather", C.c_void_p), ("ngathers", C.c_int32),
+                ("ns", C.c_void_p), ("trace_ptr", C.c_void_p), ("npar_cmp", C.c_int32),
+                ("npar_crs", C.c_int32)]
+
+
+class CBatch(C.Structure):
+    _fields_ = [("kind", C.c_void_p), ("q_cmp", C.c_void_p), ("nq_cmp", C.c_int32), ("w_cmp", C.c_int32),
+                ("A", C.c_void_p), ("nA", C.c_int32), ("B", C.c_void_p), ("nB", C.c_int32),
+                ("q_crs", C.c_void_p), ("nq_crs", C.c_int32), ("w_crs", C.c_int32)]
+
+
 _lib = None
 
 
@@ -73,6 +91,12 @@ def lib():
         L.semblance_grad.argtypes = [P, P, i32, P, P, i32, P, P, P]
         for f in (L.cmp_scan, L.crs_scan, L.stack, L.semblance_grad):
             f.restype = C.c_int
+        L.semb_batch_plan.argtypes = [P, i32, P, i64, P, P]
+        L.semb_batch_plan.restype = i64
+        L.semb_batch_workspace_bytes.argtypes = [i64, i32, i32, i32, i32]
+        L.semb_batch_workspace_bytes.restype = C.c_size_t
+        L.scan_batch.argtypes = [P, P, P, P, i64, i32, i32, P, P, C.c_size_t, P]
+        L.scan_batch.restype = C.c_int
         L.semb_last_error.restype = C.c_char_p
         L.semb_version.restype = C.c_char_p
         _lib = L
@@ -276,3 +300,53 @@ def alloc_workspace(nsamples: int, device="cuda"):
     ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
     off = (-ws.data_ptr()) % 256
     return ws[off:off + nbytes]
+
+
+# ---------------------------------------------------------------------------
+# batched scan (mixed CMP / CRS jobs, one persistent launch)
+# ---------------------------------------------------------------------------
+def batch_plan(kind, central, apert_ptr, apert_gather, ns, trace_ptr, npar_cmp: int, npar_crs: int,
+               split_params: int = 256):
+    """Tile list of a batch (host arrays in, numpy int32 [ntiles, 8] out), plus
+    (ngroups, nparts) for the workspace."""
+    arr = [np.ascontiguousarray(a, np.int32) for a in (kind, central, apert_ptr, apert_gather, ns, trace_ptr)]
+    p = [a.ctypes.data_as(C.c_void_p) for a in arr]
+    h = CBatchHost(int(arr[0].size), p[0], p[1], p[2], p[3], int(arr[4].size), p[4], p[5],
+                   int(npar_cmp), int(npar_crs))
+    ng, npart = C.c_int32(0), C.c_int32(0)
+    n = lib().semb_batch_plan(C.byref(h), int(split_params), None, 0, C.byref(ng), C.byref(npart))
+    if n < 0:
+        raise SembError(1, last_error())
+    tiles = np.zeros((max(n, 1), 8), np.int32)
+    n2 = lib().semb_batch_plan(C.byref(h), int(split_params), tiles.ctypes.data_as(C.c_void_p), int(n),
+                               C.byref(ng), C.byref(npart))
+    if n2 != n:
+        raise SembError(1, last_error())
+    return tiles[:n], int(ng.value), int(npart.value)
+
+
+def batch_workspace_bytes(nsamples: int, w_cmp: int, w_crs: int, ngroups: int, nparts: int) -> int:
+    return int(lib().semb_batch_workspace_bytes(int(nsamples), int(w_cmp), int(w_crs), int(ngroups),
+                                                int(nparts)))
+
+
+def alloc_batch_workspace(nsamples, w_cmp, w_crs, ngroups, nparts, device="cuda"):
+    import torch
+    nbytes = batch_workspace_bytes(nsamples, w_cmp, w_crs, ngroups, nparts)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def scan_batch(g: DeviceGathers, jobs: DeviceJobs, kind, q_cmp, w_cmp: int, A, B, q_crs, w_crs: int, tiles,
+               ngroups: int, nparts: int, best, s_best, stack_out, ws, stream=None):
+    """Enqueue the batched scan; tiles: device int32 [ntiles, 8] from batch_plan."""
+    import torch
+    gs, js = g.cstruct(), jobs.cstruct()
+    b = CBatch(_typed(kind, torch.int32, "kind"), _typed(q_cmp, torch.float32, "q_cmp"), int(q_cmp.numel()),
+               int(w_cmp), _typed(A, torch.float32, "A"), int(A.numel()), _typed(B, torch.float32, "B"),
+               int(B.numel()), _typed(q_crs, torch.float32, "q_crs"), int(q_crs.numel()), int(w_crs))
+    out = _outputs(best, s_best, stack_out, None)
+    _check(lib().scan_batch(C.byref(gs), C.byref(js), C.byref(b), _typed(tiles, torch.int32, "tiles"),
+                            int(tiles.shape[0]), int(ngroups), int(nparts), C.byref(out), _ptr(ws),
+                            int(ws.numel() * ws.element_size()), _stream(stream)))

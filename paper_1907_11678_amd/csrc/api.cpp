@@ -6,7 +6,9 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -82,6 +84,32 @@ semb_status check_w(int32_t w)
         if (_st != SEMB_OK) return _st;      \
     } while (0)
 
+semb::GatherView gather_view(const semb_gathers *g)
+{
+    semb::GatherView v{};
+    v.samples = g->samples;
+    v.sample_off = g->sample_off;
+    v.trace_ptr = g->trace_ptr;
+    v.ns = g->ns;
+    v.half_offset = g->half_offset;
+    v.midpoint = g->midpoint;
+    v.central_x = g->central_x;
+    v.dt = g->dt;
+    return v;
+}
+
+semb::JobView job_view(const semb_jobs *jobs, const semb_gathers *g, bool crs)
+{
+    semb::JobView v{};
+    v.central = jobs->central;
+    v.apert_ptr = crs ? jobs->apert_ptr : nullptr;
+    v.apert_gather = crs ? jobs->apert_gather : nullptr;
+    v.out_off = jobs->out_off;
+    v.njobs = jobs->njobs;
+    v.n_sblk = (g->ns_max + 63) / 64;
+    return v;
+}
+
 semb_status scan_common(int kind, const semb_gathers *g, const semb_jobs *jobs, const float *A, int32_t nA,
                         const float *B, int32_t nB, const float *q, int32_t nq, int32_t w,
                         const semb_outputs *out, void *ws, size_t ws_bytes, hipStream_t stream)
@@ -113,35 +141,23 @@ semb_status scan_common(int kind, const semb_gathers *g, const semb_jobs *jobs, 
                    "window energy launch"));
 
     semb::ScanArgs a{};
-    a.samples = g->samples;
-    a.sample_off = g->sample_off;
-    a.trace_ptr = g->trace_ptr;
-    a.ns = g->ns;
-    a.half_offset = g->half_offset;
-    a.midpoint = g->midpoint;
-    a.central_x = g->central_x;
-    a.dt = g->dt;
-    a.central = jobs->central;
-    a.apert_ptr = crs ? jobs->apert_ptr : nullptr;
-    a.apert_gather = crs ? jobs->apert_gather : nullptr;
-    a.out_off = jobs->out_off;
-    a.njobs = jobs->njobs;
-    a.n_sblk = (g->ns_max + 63) / 64;
-    a.A = A;
-    a.B = B;
-    a.q = q;
-    a.nA = crs ? nA : 1;
-    a.nB = crs ? nB : 1;
-    a.nq = nq;
-    a.npar = (int32_t)npar;
+    a.g = gather_view(g);
+    a.j = job_view(jobs, g, crs);
+    a.p.A = A;
+    a.p.B = B;
+    a.p.q = q;
+    a.p.nA = crs ? nA : 1;
+    a.p.nB = crs ? nB : 1;
+    a.p.nq = nq;
+    a.p.npar = (int32_t)npar;
+    a.p.w = w;
+    a.p.u0 = u0;
+    a.p.u1 = u1;
+    a.p.u2sq = u2sq;
     a.best = out->best;
     a.s_best = out->s_best;
     a.stack = out->stack;
     a.panel = out->panel;
-    a.u0 = u0;
-    a.u1 = u1;
-    a.u2sq = u2sq;
-    a.w = w;
     return hip_status(semb::launch_scan(kind, a, stream), crs ? "crs_scan launch" : "cmp_scan launch");
 }
 
@@ -185,9 +201,186 @@ semb_status point_common(bool grad, const semb_gathers *g, const semb_jobs *jobs
     return hip_status(semb::launch_point(kind, a, stream), "stack launch");
 }
 
+constexpr int kBatchBlock = 16;  // parameters per block of the batch kernel (8 waves x 2)
+
+bool batch_w_ok(int w) { return w == 9 || w == 11 || w == 15; }
+
+struct BatchLayout {
+    size_t plane_c, plane_r, counters, partials, total;
+};
+
+BatchLayout batch_layout(int64_t nsamples, int32_t w_cmp, int32_t w_crs, int32_t ngroups, int32_t nparts)
+{
+    BatchLayout L{};
+    const size_t plane = round_up((size_t)(nsamples > 0 ? nsamples : 0) * sizeof(float));
+    L.plane_c = 0;
+    L.plane_r = (w_cmp == w_crs) ? 0 : 3 * plane;
+    L.counters = (w_cmp == w_crs ? 3 : 6) * plane;
+    L.partials = L.counters + round_up((size_t)(1 + (ngroups > 0 ? ngroups : 0)) * sizeof(unsigned));
+    L.total = L.partials + round_up((size_t)(nparts > 0 ? nparts : 0) * 64 * sizeof(semb::Partial));
+    return L;
+}
+
 }  // namespace
 
 extern "C" {
+
+int64_t semb_batch_plan(const semb_batch_host *h, int32_t split_params, semb_tile *tiles, int64_t max_tiles,
+                        int32_t *ngroups, int32_t *nparts)
+{
+    if (!h || !h->kind || !h->central || !h->apert_ptr || !h->apert_gather || !h->ns || !h->trace_ptr) {
+        fail(SEMB_EINVAL, "semb_batch_plan: a required host array is NULL");
+        return -1;
+    }
+    if (h->njobs < 0 || h->ngathers < 1 || h->npar_cmp < 1 || h->npar_crs < 1 || split_params < 1) {
+        fail(SEMB_EINVAL, "semb_batch_plan: invalid sizes");
+        return -1;
+    }
+    const int32_t split = (split_params + kBatchBlock - 1) / kBatchBlock * kBatchBlock;
+    struct Item {
+        double cost;
+        semb_tile t;
+    };
+    std::vector<Item> items;
+    int32_t ng = 0, np = 0;
+    for (int32_t j = 0; j < h->njobs; ++j) {
+        const int32_t c = h->central[j];
+        if (c < 0 || c >= h->ngathers) {
+            fail(SEMB_EINVAL, "semb_batch_plan: job %d has central gather %d out of range", j, c);
+            return -1;
+        }
+        const bool crs = h->kind[j] == SEMB_KIND_CRS;
+        if (!crs && h->kind[j] != SEMB_KIND_CMP) {
+            fail(SEMB_EINVAL, "semb_batch_plan: job %d has an unknown kind", j);
+            return -1;
+        }
+        int64_t ntr = 0;
+        if (crs) {
+            for (int32_t k = h->apert_ptr[j]; k < h->apert_ptr[j + 1]; ++k) {
+                const int32_t gg = h->apert_gather[k];
+                if (gg < 0 || gg >= h->ngathers) {
+                    fail(SEMB_EINVAL, "semb_batch_plan: job %d has an aperture gather out of range", j);
+                    return -1;
+                }
+                ntr += h->trace_ptr[gg + 1] - h->trace_ptr[gg];
+            }
+        } else {
+            ntr = h->trace_ptr[c + 1] - h->trace_ptr[c];
+        }
+        const int32_t npar = crs ? h->npar_crs : h->npar_cmp;
+        const int32_t nsplit = (npar + split - 1) / split;
+        const int32_t nsb = (h->ns[c] + 63) / 64;
+        for (int32_t b = 0; b < nsb; ++b) {
+            const int32_t nrow = std::min(64, h->ns[c] - 64 * b);
+            const int32_t grp = nsplit > 1 ? ng++ : -1;
+            const int32_t base = nsplit > 1 ? np : 0;
+            if (nsplit > 1) np += nsplit;
+            for (int32_t sp = 0; sp < nsplit; ++sp) {
+                Item it;
+                it.t.job = j;
+                it.t.sblk = b;
+                it.t.p_begin = sp * split;
+                it.t.p_end = std::min(npar, (sp + 1) * split);
+                it.t.group = grp;
+                it.t.split = sp;
+                it.t.nsplit = nsplit;
+                it.t.part_base = base;
+                // work estimate: rows x parameters x traces (+ a fixed cost per tile)
+                it.cost = (double)nrow * (it.t.p_end - it.t.p_begin) * (double)(ntr + 4) + 4096.0;
+                items.push_back(it);
+            }
+        }
+    }
+    // longest first; ties keep job order
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+    if (ngroups) *ngroups = ng;
+    if (nparts) *nparts = np;
+    if (tiles) {
+        if ((int64_t)items.size() > max_tiles) {
+            fail(SEMB_EINVAL, "semb_batch_plan: %zu tiles do not fit in max_tiles = %lld", items.size(),
+                 (long long)max_tiles);
+            return -1;
+        }
+        for (size_t i = 0; i < items.size(); ++i) tiles[i] = items[i].t;
+    }
+    return (int64_t)items.size();
+}
+
+size_t semb_batch_workspace_bytes(int64_t nsamples, int32_t w_cmp, int32_t w_crs, int32_t ngroups,
+                                  int32_t nparts)
+{
+    return batch_layout(nsamples, w_cmp, w_crs, ngroups, nparts).total;
+}
+
+semb_status scan_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_batch *b, const semb_tile *tiles,
+                       int64_t ntiles, int32_t ngroups, int32_t nparts, const semb_outputs *out, void *ws,
+                       size_t ws_bytes, hipStream_t stream)
+{
+    TRY(check_gathers(g, true));
+    TRY(check_jobs(jobs, true, g));
+    if (!b || !b->kind || !b->q_cmp || b->nq_cmp < 1 || !b->A || b->nA < 1 || !b->B || b->nB < 1 || !b->q_crs ||
+        b->nq_crs < 1)
+        return fail(SEMB_EINVAL, "scan_batch: incomplete batch parameters");
+    if (!batch_w_ok(b->w_cmp) || !batch_w_ok(b->w_crs))
+        return fail(SEMB_EINVAL, "scan_batch supports windows 9, 11 and 15 (got %d, %d)", b->w_cmp, b->w_crs);
+    if ((long long)b->nA * b->nB * b->nq_crs > 0x7fffffffLL) return fail(SEMB_EINVAL, "too many CRS parameters");
+    if (g->ns_max > kScanCap) return fail(SEMB_EINVAL, "the scan supports ns_max <= %d", kScanCap);
+    if (ntiles < 0 || ngroups < 0 || nparts < 0) return fail(SEMB_EINVAL, "negative plan sizes");
+    if (ntiles > 0 && !tiles) return fail(SEMB_EINVAL, "tiles is NULL");
+    if (!out || !out->best || !out->s_best || !out->stack) return fail(SEMB_EINVAL, "outputs are required");
+    if (out->panel) return fail(SEMB_EINVAL, "scan_batch writes no panel (panel must be NULL)");
+    const BatchLayout lay = batch_layout(g->nsamples, b->w_cmp, b->w_crs, ngroups, nparts);
+    if (!ws || ws_bytes < lay.total || ((uintptr_t)ws % kAlign) != 0)
+        return fail(SEMB_EWORKSPACE, "workspace must be %zu bytes, 256-byte aligned (got %zu at %p)", lay.total,
+                    ws_bytes, ws);
+    char *base = static_cast<char *>(ws);
+    const size_t plane = round_up((size_t)g->nsamples * sizeof(float));
+    float *uc = reinterpret_cast<float *>(base + lay.plane_c);
+    float *ur = reinterpret_cast<float *>(base + lay.plane_r);
+    TRY(hip_status(semb::launch_window_energy(g->samples, g->sample_off, g->trace_ptr, g->ns, g->ngathers,
+                                              g->ntraces, b->w_cmp, uc, uc + plane / 4, uc + 2 * (plane / 4),
+                                              stream),
+                   "window energy launch"));
+    if (b->w_crs != b->w_cmp)
+        TRY(hip_status(semb::launch_window_energy(g->samples, g->sample_off, g->trace_ptr, g->ns, g->ngathers,
+                                                  g->ntraces, b->w_crs, ur, ur + plane / 4, ur + 2 * (plane / 4),
+                                                  stream),
+                       "window energy launch"));
+    semb::BatchArgs a{};
+    a.g = gather_view(g);
+    a.j = job_view(jobs, g, true);
+    a.kind = b->kind;
+    a.pc.A = nullptr;
+    a.pc.B = nullptr;
+    a.pc.q = b->q_cmp;
+    a.pc.nA = a.pc.nB = 1;
+    a.pc.nq = b->nq_cmp;
+    a.pc.npar = b->nq_cmp;
+    a.pc.w = b->w_cmp;
+    a.pc.u0 = uc;
+    a.pc.u1 = uc + plane / 4;
+    a.pc.u2sq = uc + 2 * (plane / 4);
+    a.pr.A = b->A;
+    a.pr.B = b->B;
+    a.pr.q = b->q_crs;
+    a.pr.nA = b->nA;
+    a.pr.nB = b->nB;
+    a.pr.nq = b->nq_crs;
+    a.pr.npar = b->nA * b->nB * b->nq_crs;
+    a.pr.w = b->w_crs;
+    a.pr.u0 = ur;
+    a.pr.u1 = ur + plane / 4;
+    a.pr.u2sq = ur + 2 * (plane / 4);
+    a.tiles = tiles;
+    a.ntiles = ntiles;
+    a.counters = reinterpret_cast<unsigned int *>(base + lay.counters);
+    a.partials = reinterpret_cast<semb::Partial *>(base + lay.partials);
+    a.best = out->best;
+    a.s_best = out->s_best;
+    a.stack = out->stack;
+    return hip_status(semb::launch_batch(a, ngroups, stream), "scan_batch launch");
+}
+
 
 size_t semb_workspace_bytes(int64_t nsamples)
 {

@@ -10,9 +10,8 @@
 
 namespace semb {
 
-// Everything a scan kernel needs, passed by value as the kernel argument.
-struct ScanArgs {
-    // gathers
+// The gathers as the kernels see them.
+struct GatherView {
     const float *samples;
     const int64_t *sample_off;
     const int32_t *trace_ptr;
@@ -21,28 +20,63 @@ struct ScanArgs {
     const float *midpoint;
     const float *central_x;
     float dt;
-    // jobs
+};
+
+// Jobs: central gather, aperture (CSR; NULL = the central gather alone) and
+// output row offset; n_sblk = output-sample blocks per job (ceil(ns_max/64)).
+struct JobView {
     const int32_t *central;
-    const int32_t *apert_ptr;    // NULL: aperture = {central}
+    const int32_t *apert_ptr;
     const int32_t *apert_gather;
     const int64_t *out_off;
     int32_t njobs;
-    int32_t n_sblk;              // output-sample blocks per job (ceil(ns_max / 64))
-    // parameters; flat index = (iA * nB + iB) * nq + iq
+    int32_t n_sblk;
+};
+
+// One parameter grid (flat index (iA * nB + iB) * nq + iq) with the window
+// and the window-energy planes for that window (workspace, one per sample).
+struct ParamView {
     const float *A;
     const float *B;
     const float *q;
     int32_t nA, nB, nq, npar;
-    // outputs
+    int32_t w;
+    const float *u0;
+    const float *u1;
+    const float *u2sq;
+};
+
+struct ScanArgs {
+    GatherView g;
+    JobView j;
+    ParamView p;
     int32_t *best;
     float *s_best;
     float *stack;
     float *panel;
-    // window energy in Gram form (workspace), one per sample
-    const float *u0;
-    const float *u1;
-    const float *u2sq;
-    int32_t w;
+};
+
+// One partial pick of a split tile: best S, its flat index, its stack.
+struct Partial {
+    float S;
+    int32_t I;
+    float stack;
+    float pad;
+};
+
+struct BatchArgs {
+    GatherView g;
+    JobView j;
+    const int32_t *kind;      // [njobs]
+    ParamView pc;             // CMP jobs
+    ParamView pr;             // CRS jobs
+    const semb_tile *tiles;   // [ntiles], processed in this order
+    int64_t ntiles;
+    unsigned int *counters;   // [1 + ngroups]: tile counter, then finished splits per group
+    Partial *partials;        // [nparts * 64]
+    int32_t *best;
+    float *s_best;
+    float *stack;
 };
 
 struct PointArgs {
@@ -75,6 +109,7 @@ hipError_t launch_window_energy(const float *samples, const int64_t *sample_off,
                                 int32_t ntraces, int32_t w, float *u0, float *u1, float *u2sq,
                                 hipStream_t stream);
 hipError_t launch_scan(int kind, const ScanArgs &a, hipStream_t stream);
+hipError_t launch_batch(const BatchArgs &a, int ngroups, hipStream_t stream);
 hipError_t launch_point(int kind, const PointArgs &a, hipStream_t stream);
 hipError_t launch_grad(int kind, const PointArgs &a, hipStream_t stream);
 

@@ -139,101 +139,106 @@ window_energy_kernel(const float *__restrict__ samples, const int64_t *__restric
 }
 
 // ---------------------------------------------------------------------------
-// The scan.  KIND: SEMB_KIND_CMP / SEMB_KIND_CRS.  W: window.  P: parameters
-// per lane.  NW: waves per workgroup.  CAP: LDS sample positions per stage.
+// One tile of the scan: output samples 64*sblk .. 64*sblk+63 of a job and
+// flat parameter indices [pbeg, pend).  KIND: SEMB_KIND_CMP / SEMB_KIND_CRS.
+// W: window.  P: parameters per lane.  NW: waves per workgroup.  CAP: LDS
+// sample positions per stage.  BRANCHY: windows behind a per-parameter branch
+// (skips off-trace windows) instead of the branch-free form (keeps every
+// window's loads in flight).
 // ---------------------------------------------------------------------------
-// WPE: minimum waves per SIMD the register allocation must allow.
-template <int KIND, int W, int P, int NW, int CAP, int WPE>
-__global__ void __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(WPE)))
-scan_kernel(ScanArgs a)
+template <int KIND, int W, int P, int NW, int CAP>
+struct StageLds {
+    float lf[CAP];                                  // staged samples
+    float lu0[CAP], lu1[CAP], lu2[CAP];             // their window energy (Gram form)
+    double2 tab[KIND == SEMB_KIND_CRS ? NW * P : 1][WAVE];  // CRS: (2 alpha + beta, alpha^2 + gamma)
+    double t_cc[WAVE];                              // h^2/dt^2 per staged trace
+    int2 tinfo[WAVE];                               // (base - lo, ns - 1 - W)
+    long long t_src[WAVE];                          // element of the first staged sample
+    int t_len[WAVE], t_base[WAVE];
+    float t_dm[WAVE];
+    double pq[NW * P], pA[NW * P], pB[NW * P];      // the current parameter block
+    int ag_s[SEMB_APERT_LIMIT];
+    int ag_cum[SEMB_APERT_LIMIT + 1];
+    int nfit;
+};
+
+// All threads of the workgroup call this together.  On return, lane l of
+// wave 0 holds the pick of output sample 64*sblk + l over [pbeg, pend):
+// bS (negative if the lane's sample lies beyond the job's trace length), bI,
+// bSt.  panel: optional [row][npar] semblance of every cell.
+template <int KIND, int W, int P, int NW, int CAP, bool BRANCHY>
+__device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv, const ParamView &pv,
+                                          StageLds<KIND, W, P, NW, CAP> &L, int job, int sblk, int pbeg,
+                                          int pend, float *panel, float &bS, int &bI, float &bSt)
 {
     constexpr int HW = (W - 1) / 2;
     constexpr int NT = NW * P;  // parameters per block
-    constexpr int RMAX = WAVE;  // traces per stage (one per lane of wave 0)
     constexpr bool CRS = KIND == SEMB_KIND_CRS;
-
-    __shared__ float lf[CAP];                    // staged samples
-    __shared__ float lu0[CAP], lu1[CAP], lu2[CAP];  // their window energy (Gram form)
-    __shared__ double2 tab[CRS ? NT : 1][RMAX];  // CRS: (2 alpha + beta, alpha^2 + gamma)
-    __shared__ double t_cc[RMAX];                // h^2/dt^2 per staged trace
-    __shared__ int2 tinfo[RMAX];                 // (base - lo, ns - 1 - W)
-    __shared__ long long t_src[RMAX];            // element of the first staged sample
-    __shared__ int t_len[RMAX], t_base[RMAX];
-    __shared__ float t_dm[RMAX];
-    __shared__ double pq[NT], pA[NT], pB[NT];    // this block's parameters
-    __shared__ int ag_s[SEMB_APERT_LIMIT];
-    __shared__ int ag_cum[SEMB_APERT_LIMIT + 1];
-    __shared__ int sh_nfit;
 
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
 
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int job = tile / a.n_sblk;
-    const int sblk = tile - job * a.n_sblk;
-    if (job >= a.njobs) return;
-    const int c = a.central[job];
-    const int nsc = a.ns[c];
+    const int c = jv.central[job];
+    const int nsc = g.ns[c];
     const int s0 = sblk * WAVE;
-    if (s0 >= nsc) return;  // uniform over the workgroup, before any barrier
     const int s1 = min(s0 + WAVE, nsc) - 1;
     const int s = s0 + lane;
     const bool lane_on = s < nsc;
 
+    bS = -1.f;
+    bSt = 0.f;
+    bI = pbeg;
+
+    __syncthreads();  // the previous tile (persistent loop) is done with L
     // ---- the job's aperture: gathers and cumulative trace counts ----------
     int na = 1, afirst = -1;
-    if (CRS && a.apert_ptr != nullptr) {
-        afirst = a.apert_ptr[job];
-        na = min(a.apert_ptr[job + 1] - afirst, SEMB_APERT_LIMIT);
+    if (CRS && jv.apert_ptr != nullptr) {
+        afirst = jv.apert_ptr[job];
+        na = min(jv.apert_ptr[job + 1] - afirst, SEMB_APERT_LIMIT);
         na = max(na, 0);
     }
-    if (tid < na) ag_s[tid] = (afirst < 0) ? c : a.apert_gather[afirst + tid];
+    if (tid < na) L.ag_s[tid] = (afirst < 0) ? c : jv.apert_gather[afirst + tid];
     __syncthreads();
     if (tid == 0) {
         int acc = 0;
-        ag_cum[0] = 0;
+        L.ag_cum[0] = 0;
         for (int k = 0; k < na; ++k) {
-            const int g = ag_s[k];
-            acc += a.trace_ptr[g + 1] - a.trace_ptr[g];
-            ag_cum[k + 1] = acc;
+            const int gg = L.ag_s[k];
+            acc += g.trace_ptr[gg + 1] - g.trace_ptr[gg];
+            L.ag_cum[k + 1] = acc;
         }
     }
     __syncthreads();
-    const int ntr = ag_cum[na];
-    const double xc = CRS ? (double)a.central_x[c] : 0.0;
-    const double inv_dt = 1.0 / (double)a.dt;
+    const int ntr = L.ag_cum[na];
+    const double xc = CRS ? (double)g.central_x[c] : 0.0;
+    const double inv_dt = 1.0 / (double)g.dt;
 
     const double sd = (double)s;
     const double s2 = sd * sd;
 
-    float bS = -1.f, bSt = 0.f;
-    int bI = 0;
-
-    for (int pb = 0; pb < a.npar; pb += NT) {
-        const int pe = min(pb + NT, a.npar);
-        // bounds of this block's parameters (wave-uniform)
+    for (int pb = pbeg; pb < pend; pb += NT) {
         // ---- this block's parameters, decoded once by wave 0 (one per lane) into
         // LDS, with their bounds reduced across the wave.  The previous block
         // ended with a barrier, so the parameter arrays are free.
         double qlo = 0.0, qhi = 0.0, Alo = 0.0, Ahi = 0.0, Blo = 0.0, Bhi = 0.0;
         if (wv == 0) {
             const int th = pb + lane;
-            const bool on = lane < NT && th < a.npar;
+            const bool on = lane < NT && th < pend;
             double qv = 0.0, Av = 0.0, Bv = 0.0;
             if (on) {
-                const int iq = th % a.nq;
-                qv = a.q[iq];
+                const int iq = th % pv.nq;
+                qv = pv.q[iq];
                 if (CRS) {
-                    const int rest = th / a.nq;
-                    Bv = a.B[rest % a.nB];
-                    Av = a.A[rest / a.nB];
+                    const int rest = th / pv.nq;
+                    Bv = pv.B[rest % pv.nB];
+                    Av = pv.A[rest / pv.nB];
                 }
             }
             if (lane < NT) {
-                pq[lane] = qv;
-                pA[lane] = Av;
-                pB[lane] = Bv;
+                L.pq[lane] = qv;
+                L.pA[lane] = Av;
+                L.pB[lane] = Bv;
             }
             qlo = wave_min(on ? qv : 1e300);
             qhi = wave_max(on ? qv : -1e300);
@@ -263,16 +268,16 @@ scan_kernel(ScanArgs a)
                 double cc = 0.0, dm = 0.0;
                 if (t < ntr) {
                     int k = 0;
-                    while (k + 1 < na && ag_cum[k + 1] <= t) ++k;
-                    const int g = ag_s[k];
-                    const int li = t - ag_cum[k];
-                    const int i = a.trace_ptr[g] + li;
-                    nsg = a.ns[g];
-                    src = a.sample_off[g] + (long long)li * nsg;
-                    const double h = a.half_offset[i];
+                    while (k + 1 < na && L.ag_cum[k + 1] <= t) ++k;
+                    const int gg = L.ag_s[k];
+                    const int li = t - L.ag_cum[k];
+                    const int i = g.trace_ptr[gg] + li;
+                    nsg = g.ns[gg];
+                    src = g.sample_off[gg] + (long long)li * nsg;
+                    const double h = g.half_offset[i];
                     cc = h * h * inv_dt * inv_dt;
                     // the displacement as the kernels use it: rounded to FP32
-                    dm = CRS ? (double)(float)((double)a.midpoint[i] - xc) : 0.0;
+                    dm = CRS ? (double)(float)((double)g.midpoint[i] - xc) : 0.0;
                     // bounds of tau^2 over the tile (interval arithmetic, FP64)
                     double Tlo, Thi;
                     const double gl = fmin(qlo * cc, qhi * cc), gh = fmax(qlo * cc, qhi * cc);
@@ -318,18 +323,18 @@ scan_kernel(ScanArgs a)
                     if (lane == 0) len = min(len, CAP), incl = len;
                 }
                 if (lane < nfit) {
-                    t_src[lane] = src + lo;
-                    t_len[lane] = len;
-                    t_base[lane] = incl - len;
+                    L.t_src[lane] = src + lo;
+                    L.t_len[lane] = len;
+                    L.t_base[lane] = incl - len;
                     // a trace without staged samples gets lim = -1: none of its windows count
-                    tinfo[lane] = make_int2(incl - len - lo, len > 0 ? nsg - 1 - W : -1);
-                    t_cc[lane] = cc;
-                    t_dm[lane] = (float)dm;
+                    L.tinfo[lane] = make_int2(incl - len - lo, len > 0 ? nsg - 1 - W : -1);
+                    L.t_cc[lane] = cc;
+                    L.t_dm[lane] = (float)dm;
                 }
-                if (lane == 0) sh_nfit = nfit;
+                if (lane == 0) L.nfit = nfit;
             }
             __syncthreads();
-            const int nfit = sh_nfit;
+            const int nfit = L.nfit;
 
             // ---- stage the samples and their window energy -------------------
             // Direct global->LDS loads (global_load_lds_dword): lane l of a wave
@@ -337,15 +342,15 @@ scan_kernel(ScanArgs a)
             // base + p0 + l without passing through registers, so every load of
             // the chunk is in flight at once; the barrier below waits for them.
             for (int r = wv; r < nfit; r += NW) {
-                const long long src = t_src[r];
-                const int len = t_len[r], base = t_base[r];
+                const long long src = L.t_src[r];
+                const int len = L.t_len[r], base = L.t_base[r];
                 for (int p0 = 0; p0 < len; p0 += WAVE) {
                     if (p0 + lane < len) {
                         const long long gi = src + p0 + lane;
-                        lds_dma(a.samples + gi, &lf[base + p0]);
-                        lds_dma(a.u0 + gi, &lu0[base + p0]);
-                        lds_dma(a.u1 + gi, &lu1[base + p0]);
-                        lds_dma(a.u2sq + gi, &lu2[base + p0]);
+                        lds_dma(g.samples + gi, &L.lf[base + p0]);
+                        lds_dma(pv.u0 + gi, &L.lu0[base + p0]);
+                        lds_dma(pv.u1 + gi, &L.lu1[base + p0]);
+                        lds_dma(pv.u2sq + gi, &L.lu2[base + p0]);
                     }
                 }
             }
@@ -354,10 +359,10 @@ scan_kernel(ScanArgs a)
                 //   u1 = 2 alpha + beta, u0 = alpha^2 + gamma (FP64)
                 for (int pl = wv; pl < NT; pl += NW) {
                     if (lane < nfit) {
-                        const double dmr = t_dm[lane];
-                        const double al = pA[pl] * 2.0 * dmr * inv_dt;
-                        const double be = pB[pl] * 2.0 * dmr * dmr * inv_dt;
-                        tab[pl][lane] = make_double2(2.0 * al + be, fma(al, al, pq[pl] * t_cc[lane]));
+                        const double dmr = L.t_dm[lane];
+                        const double al = L.pA[pl] * 2.0 * dmr * inv_dt;
+                        const double be = L.pB[pl] * 2.0 * dmr * dmr * inv_dt;
+                        L.tab[pl][lane] = make_double2(2.0 * al + be, fma(al, al, L.pq[pl] * L.t_cc[lane]));
                     }
                 }
             }
@@ -365,24 +370,24 @@ scan_kernel(ScanArgs a)
 
             // ---- the hot loop: traces outer, this lane's P parameters inner ----
             // First the P intersections (independent FP64 chains), then the P
-            // windows without branches: a window that is off the trace reads a
-            // harmless in-range LDS word with zero weights, so the loads of all
-            // P windows can be in flight together.
+            // windows.  In the branch-free form a window that is off the trace
+            // reads a harmless in-range LDS word with zero weights, so the loads
+            // of all P windows can be in flight together.
             double qd[P];  // this wave's parameters (CMP), held in scalar registers
 #pragma unroll
-            for (int p = 0; p < P; ++p) qd[p] = to_sgpr(pq[wv * P + p]);
+            for (int p = 0; p < P; ++p) qd[p] = to_sgpr(L.pq[wv * P + p]);
             if (lane_on) {
                 for (int r = 0; r < nfit; ++r) {
-                    const int2 ti = tinfo[r];
+                    const int2 ti = L.tinfo[r];
                     if (ti.y < 0) continue;  // uniform: no staged window on this trace
-                    const double cc = t_cc[r];
+                    const double cc = L.t_cc[r];
                     int idx[P];
                     float xw[P], uw[P], vm[P];
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         double num;
                         if (CRS) {
-                            const double2 tv = tab[wv * P + p][r];
+                            const double2 tv = L.tab[wv * P + p][r];
                             num = fma(sd, tv.x, tv.y);
                         } else {
                             num = qd[p] * cc;
@@ -397,17 +402,18 @@ scan_kernel(ScanArgs a)
                     }
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
+                        if (BRANCHY && vm[p] == 0.f) continue;
                         const int id = idx[p];
                         float fw[W + 1];
 #pragma unroll
-                        for (int j = 0; j <= W; ++j) fw[j] = lf[id + j];
+                        for (int j = 0; j <= W; ++j) fw[j] = L.lf[id + j];
 #pragma unroll
                         for (int j = 0; j < W; ++j) {
                             U[p][j] = fmaf(uw[p], fw[j], U[p][j]);
                             U[p][j] = fmaf(xw[p], fw[j + 1], U[p][j]);
                         }
-                        const float tq = fmaf(xw[p], lu1[id], lu0[id]);
-                        D[p] = fmaf(vm[p], fmaf(tq, tq, lu2[id]), D[p]);
+                        const float tq = fmaf(xw[p], L.lu1[id], L.lu0[id]);
+                        D[p] = fmaf(vm[p], fmaf(tq, tq, L.lu2[id]), D[p]);
                         Mc[p] += vm[p];
                     }
                 }
@@ -418,20 +424,20 @@ scan_kernel(ScanArgs a)
 
         // ---- semblance of this block's parameters; running pick --------------
         if (lane_on) {
-            const int64_t row = a.out_off[job] + s;
+            const int64_t row = jv.out_off[job] + s;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int th = pb + wv * P + p;
-                if (th < a.npar) {
-                    float N = 0.f, L = 0.f;
+                if (th < pend) {
+                    float N = 0.f, Ls = 0.f;
 #pragma unroll
                     for (int j = 0; j < W; ++j) {
                         N = fmaf(U[p][j], U[p][j], N);
-                        L += U[p][j];
+                        Ls += U[p][j];
                     }
                     const float S = (Mc[p] > 0.f && D[p] > 0.f) ? N / (Mc[p] * D[p]) : 0.f;
-                    const float st = (Mc[p] > 0.f) ? L / (Mc[p] * (float)W) : 0.f;
-                    if (a.panel) a.panel[row * a.npar + th] = S;
+                    const float st = (Mc[p] > 0.f) ? Ls / (Mc[p] * (float)W) : 0.f;
+                    if (panel) panel[row * pv.npar + th] = S;
                     if (S > bS) {  // parameters visited in increasing index: first max wins
                         bS = S;
                         bI = th;
@@ -443,15 +449,15 @@ scan_kernel(ScanArgs a)
     }
 
     // ---- pick across the waves (largest S, then smallest index) --------------
-    float *rS = lf;  // reuse the stage buffers
-    int *rI = reinterpret_cast<int *>(lu0);
-    float *rT = lu1;
+    float *rS = L.lf;  // reuse the stage buffers
+    int *rI = reinterpret_cast<int *>(L.lu0);
+    float *rT = L.lu1;
     __syncthreads();
     rS[wv * WAVE + lane] = bS;
     rI[wv * WAVE + lane] = bI;
     rT[wv * WAVE + lane] = bSt;
     __syncthreads();
-    if (wv == 0 && lane_on) {
+    if (wv == 0) {
 #pragma unroll
         for (int v = 1; v < NW; ++v) {
             const float S = rS[v * WAVE + lane];
@@ -462,29 +468,59 @@ scan_kernel(ScanArgs a)
                 bSt = rT[v * WAVE + lane];
             }
         }
-        const int64_t row = a.out_off[job] + s;
+    }
+}
+
+// Tile shapes (measured on MI355X, see the design notes).  CMP: 4 parameters
+// per lane in 4 waves at <= 128 VGPRs (4 waves per SIMD), 2048-position
+// stage, windows behind a branch.  CRS, whose per-evaluation table read and
+// wider apertures favour occupancy: 2 parameters per lane in 8 waves,
+// 3072-position stage, branch-free windows.
+template <int KIND, int W>
+struct Shape;
+template <int W>
+struct Shape<SEMB_KIND_CMP, W> {
+    static constexpr int NW = 4, P = W <= 15 ? 4 : 2, CAP = 2048, WPE = 4;
+    static constexpr bool BRANCHY = true;
+};
+template <int W>
+struct Shape<SEMB_KIND_CRS, W> {
+    static constexpr int NW = 8, P = 2, CAP = 3072, WPE = 1;
+    static constexpr bool BRANCHY = false;
+};
+
+// The exhaustive scan: one workgroup per (job, sample block), all parameters.
+template <int KIND, int W>
+__global__ void __launch_bounds__((Shape<KIND, W>::NW * WAVE))
+__attribute__((amdgpu_waves_per_eu(Shape<KIND, W>::WPE)))
+scan_kernel(ScanArgs a)
+{
+    using S = Shape<KIND, W>;
+    __shared__ StageLds<KIND, W, S::P, S::NW, S::CAP> L;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int job = tile / a.j.n_sblk;
+    const int sblk = tile - job * a.j.n_sblk;
+    if (job >= a.j.njobs) return;
+    if (sblk * WAVE >= a.g.ns[a.j.central[job]]) return;  // uniform, before any barrier
+    float bS, bSt;
+    int bI;
+    scan_tile<KIND, W, S::P, S::NW, S::CAP, S::BRANCHY>(a.g, a.j, a.p, L, job, sblk, 0, a.p.npar, a.panel,
+                                                          bS, bI, bSt);
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (threadIdx.x < WAVE && bS >= 0.f) {
+        const int64_t row = a.j.out_off[job] + sblk * WAVE + lane;
         a.best[row] = bI;
-        a.s_best[row] = bS < 0.f ? 0.f : bS;
+        a.s_best[row] = bS;
         a.stack[row] = bSt;
     }
 }
 
-// Tile shape per kind (measured on MI355X, see the design notes): CMP keeps 4
-// parameters per lane in 4 waves at <= 128 VGPRs (4 waves per SIMD); CRS, whose
-// per-eval table read and larger apertures favour occupancy, uses 2
-// parameters per lane in 8 waves.  Stage capacity: 2048 positions (CMP, four
-// workgroups per CU), 3072 (CRS, two workgroups per CU).
 template <int KIND, int W>
 hipError_t launch_w(const ScanArgs &a, hipStream_t stream)
 {
-    constexpr bool CRS = KIND == SEMB_KIND_CRS;
-    constexpr int NW = CRS ? 8 : 4;
-    constexpr int P = CRS ? 2 : (W <= 15 ? 4 : 2);
-    constexpr int WPE = CRS ? 1 : 4;
-    constexpr int CAP = CRS ? 3072 : 2048;
-    const long long nblk = (long long)a.njobs * a.n_sblk;
+    const long long nblk = (long long)a.j.njobs * a.j.n_sblk;
     if (nblk == 0) return hipSuccess;
-    hipLaunchKernelGGL((scan_kernel<KIND, W, P, NW, CAP, WPE>), dim3((unsigned)nblk), dim3(NW * WAVE), 0,
+    hipLaunchKernelGGL((scan_kernel<KIND, W>), dim3((unsigned)nblk), dim3(Shape<KIND, W>::NW * WAVE), 0,
                        stream, a);
     return hipGetLastError();
 }
@@ -492,7 +528,7 @@ hipError_t launch_w(const ScanArgs &a, hipStream_t stream)
 template <int KIND>
 hipError_t launch_kind(const ScanArgs &a, hipStream_t stream)
 {
-    switch (a.w) {
+    switch (a.p.w) {
     case 1: return launch_w<KIND, 1>(a, stream);
     case 3: return launch_w<KIND, 3>(a, stream);
     case 5: return launch_w<KIND, 5>(a, stream);
@@ -513,6 +549,128 @@ hipError_t launch_kind(const ScanArgs &a, hipStream_t stream)
     }
 }
 
+// ---------------------------------------------------------------------------
+// The batched scan: a persistent grid takes tiles of a mixed CMP/CRS job list
+// from an atomic counter (longest tiles first, as planned on the host).  A
+// tile that covers all parameters of its (job, sample block) writes the
+// outputs; otherwise it stores a partial pick, and the last tile of its group
+// to finish (counted with an atomic, after a release fence) merges the
+// group's partials in split order.  Both kinds share the 8-wave shape.
+// ---------------------------------------------------------------------------
+constexpr int BATCH_NW = 8;
+constexpr int BATCH_P_CMP = 2;
+constexpr int BATCH_P_CRS = 2;
+constexpr int BATCH_CAP = 3072;
+
+__global__ void reset_counters_kernel(unsigned int *c, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = 0u;
+}
+
+template <int WC, int WR>
+__global__ void __launch_bounds__(BATCH_NW * WAVE) __attribute__((amdgpu_waves_per_eu(4)))
+batch_kernel(BatchArgs b)
+{
+    using LC = StageLds<SEMB_KIND_CMP, WC, BATCH_P_CMP, BATCH_NW, BATCH_CAP>;
+    using LR = StageLds<SEMB_KIND_CRS, WR, BATCH_P_CRS, BATCH_NW, BATCH_CAP>;
+    __shared__ union U {
+        LC c;
+        LR r;
+    } L;
+    __shared__ long long sh_tile;
+    __shared__ int sh_last;
+    const int lane = threadIdx.x & (WAVE - 1);
+
+    for (;;) {
+        __syncthreads();  // everyone has read the previous tile index
+        if (threadIdx.x == 0) sh_tile = (long long)atomicAdd(&b.counters[0], 1u);
+        __syncthreads();
+        const long long t = sh_tile;
+        if (t >= b.ntiles) break;  // uniform: every workgroup leaves once the list is drained
+        const semb_tile tl = b.tiles[t];
+        const int kind = b.kind[tl.job];
+        float bS, bSt;
+        int bI;
+        if (kind == SEMB_KIND_CMP)
+            scan_tile<SEMB_KIND_CMP, WC, BATCH_P_CMP, BATCH_NW, BATCH_CAP, true>(
+                b.g, b.j, b.pc, L.c, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, bS, bI, bSt);
+        else
+            scan_tile<SEMB_KIND_CRS, WR, BATCH_P_CRS, BATCH_NW, BATCH_CAP, false>(
+                b.g, b.j, b.pr, L.r, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, bS, bI, bSt);
+        const int64_t row = b.j.out_off[tl.job] + tl.sblk * WAVE + lane;
+        if (tl.nsplit <= 1) {
+            if (threadIdx.x < WAVE && bS >= 0.f) {
+                b.best[row] = bI;
+                b.s_best[row] = bS;
+                b.stack[row] = bSt;
+            }
+            continue;
+        }
+        Partial *part = b.partials + (int64_t)tl.part_base * WAVE;
+        if (threadIdx.x < WAVE) {
+            Partial pt;
+            pt.S = bS;
+            pt.I = bI;
+            pt.stack = bSt;
+            pt.pad = 0.f;
+            part[(int64_t)tl.split * WAVE + lane] = pt;
+            __threadfence();  // release the partial before counting this split done
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) sh_last = (atomicAdd(&b.counters[1 + tl.group], 1u) == (unsigned)(tl.nsplit - 1));
+        __syncthreads();
+        if (sh_last && threadIdx.x < WAVE) {
+            __threadfence();  // acquire the other splits' partials
+            float mS = -2.f, mT = 0.f;
+            int mI = 0;
+            for (int sp = 0; sp < tl.nsplit; ++sp) {
+                const Partial q = part[(int64_t)sp * WAVE + lane];
+                if (q.S > mS) {  // splits cover increasing index ranges: first max wins
+                    mS = q.S;
+                    mI = q.I;
+                    mT = q.stack;
+                }
+            }
+            if (mS >= 0.f) {
+                b.best[row] = mI;
+                b.s_best[row] = mS;
+                b.stack[row] = mT;
+            }
+        }
+    }
+}
+
+template <int WC>
+hipError_t launch_batch_wc(const BatchArgs &a, dim3 grid, hipStream_t stream)
+{
+    switch (a.pr.w) {
+    case 9: hipLaunchKernelGGL((batch_kernel<WC, 9>), grid, dim3(BATCH_NW * WAVE), 0, stream, a); break;
+    case 11: hipLaunchKernelGGL((batch_kernel<WC, 11>), grid, dim3(BATCH_NW * WAVE), 0, stream, a); break;
+    case 15: hipLaunchKernelGGL((batch_kernel<WC, 15>), grid, dim3(BATCH_NW * WAVE), 0, stream, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int WC, int WR>
+int batch_blocks_per_cu()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<WC, WR>, BATCH_NW * WAVE, 0) != hipSuccess)
+        n = 1;
+    return n < 1 ? 1 : n;
+}
+
+int batch_occupancy(int wc, int wr)
+{
+#define SEMB_OCC(A, B) if (wc == A && wr == B) return batch_blocks_per_cu<A, B>();
+    SEMB_OCC(9, 9) SEMB_OCC(9, 11) SEMB_OCC(9, 15)
+    SEMB_OCC(11, 9) SEMB_OCC(11, 11) SEMB_OCC(11, 15)
+    SEMB_OCC(15, 9) SEMB_OCC(15, 11) SEMB_OCC(15, 15)
+#undef SEMB_OCC
+    return 1;
+}
+
 }  // namespace
 
 hipError_t launch_window_energy(const float *samples, const int64_t *sample_off,
@@ -530,6 +688,26 @@ hipError_t launch_scan(int kind, const ScanArgs &a, hipStream_t stream)
 {
     return kind == SEMB_KIND_CMP ? launch_kind<SEMB_KIND_CMP>(a, stream)
                                  : launch_kind<SEMB_KIND_CRS>(a, stream);
+}
+
+hipError_t launch_batch(const BatchArgs &a, int ngroups, hipStream_t stream)
+{
+    const int ncount = 1 + ngroups;
+    hipLaunchKernelGGL(reset_counters_kernel, dim3((ncount + 255) / 256 < 1024 ? (ncount + 255) / 256 : 1024),
+                       dim3(256), 0, stream, a.counters, ncount);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.ntiles == 0) return e;
+    int dev = 0, cus = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    const long long want = (long long)cus * batch_occupancy(a.pc.w, a.pr.w);
+    const dim3 grid((unsigned)(want < a.ntiles ? want : a.ntiles));
+    switch (a.pc.w) {
+    case 9: return launch_batch_wc<9>(a, grid, stream);
+    case 11: return launch_batch_wc<11>(a, grid, stream);
+    case 15: return launch_batch_wc<15>(a, grid, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace semb

@@ -483,3 +483,61 @@ def batched_kinds(n: int = 4096, n_cmp: int = 2867, seed: int = ROOT_SEED + 3) -
     kinds = np.ones(n, np.int32)
     kinds[_rng(seed, 3, 0).permutation(n)[:n_cmp]] = 0
     return kinds
+
+
+@dataclass
+class BatchWorkload:
+    """Mixed CMP/CRS jobs on one line of uneven gathers (one job per gather)."""
+    gathers: Gathers
+    jobs: Jobs                 # aperture CSR: the central alone for CMP jobs
+    kind: np.ndarray           # int32 [njobs], 0 = CMP, 1 = CRS
+    grid_cmp: Grid
+    grid_crs: Grid
+    w_cmp: int
+    w_crs: int
+
+    def subset(self, kind: int) -> Jobs:
+        """The jobs of one kind (same output rows as in the batch)."""
+        sel = np.nonzero(self.kind == kind)[0]
+        ptr, ag = [0], []
+        for j in sel:
+            ag.extend(self.jobs.apert_gather[self.jobs.apert_ptr[j]:self.jobs.apert_ptr[j + 1]])
+            ptr.append(len(ag))
+        return Jobs(central=self.jobs.central[sel].copy(), apert_ptr=np.asarray(ptr, np.int32),
+                    apert_gather=np.asarray(ag, np.int32), out_off=self.jobs.out_off[sel].copy(),
+                    n_out=self.jobs.n_out)
+
+
+def batched_line(ids=None, half_aperture: int = 2) -> BatchWorkload:
+    """The batched workload: 4096 gathers of uneven fold (8..120) and length
+    (500..2000 samples at 4 ms); 2867 CMP jobs (101 velocities 1500..4500 m/s,
+    window 11) and 1229 CRS jobs (A 11 x B 11 x v 21 over the CRS line's ranges,
+    +-2 neighbouring gathers truncated at the line ends, window 9).
+
+    ids: optional subset of gathers (e.g. a contiguous stretch); every job is
+    then restricted to gathers inside the subset."""
+    spec = batched_line_spec()
+    kinds_all = batched_kinds(spec.ngathers)
+    ids = list(range(spec.ngathers)) if ids is None else list(ids)
+    gs = line_gathers(spec, ids)
+    pos = {g: i for i, g in enumerate(ids)}
+    kind = np.array([kinds_all[g] for g in ids], np.int32)
+    ptr, ag = [0], []
+    for g, k in zip(ids, kind):
+        if k == 0:
+            ag.append(pos[g])
+        else:
+            ag.extend(pos[x] for x in range(g - half_aperture, g + half_aperture + 1) if x in pos)
+        ptr.append(len(ag))
+    central = np.arange(len(ids), dtype=np.int32)
+    ns = gs.ns.astype(np.int64)
+    out_off = np.zeros(len(ids), np.int64)
+    if len(ids) > 1:
+        out_off[1:] = np.cumsum(ns)[:-1]
+    jobs = Jobs(central=central, apert_ptr=np.asarray(ptr, np.int32), apert_gather=np.asarray(ag, np.int32),
+                out_off=out_off, n_out=int(ns.sum()))
+    return BatchWorkload(gathers=gs, jobs=jobs, kind=kind,
+                         grid_cmp=Grid(q=velocity_grid(1500.0, 4500.0, 101)),
+                         grid_crs=Grid(A=uniform_grid(-5e-4, 5e-4, 11), B=uniform_grid(-1e-7, 1e-7, 11),
+                                       q=velocity_grid(1500.0, 4500.0, 21)),
+                         w_cmp=11, w_crs=9)

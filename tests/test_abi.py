@@ -134,3 +134,43 @@ def test_point_calls_validate(semb):
 
 def test_version(semb):
     assert "gfx950" in semb.version()
+
+
+def test_batch_plan_host_only(semb):
+    """The planner is host code: tiles cover every (job, sample block,
+    parameter) once, longest first, with consistent groups."""
+    import numpy as np
+    kind = np.array([0, 1, 1, 0], np.int32)
+    central = np.arange(4, dtype=np.int32)
+    apert_ptr = np.array([0, 1, 4, 6, 7], np.int32)
+    apert_gather = np.array([0, 0, 1, 2, 2, 3, 3], np.int32)
+    ns = np.array([100, 64, 300, 1], np.int32)
+    trace_ptr = np.array([0, 5, 7, 20, 22], np.int32)
+    tiles, ng, npart = semb.batch_plan(kind, central, apert_ptr, apert_gather, ns, trace_ptr, 101, 2541, 256)
+    cover = {}
+    for t in tiles:
+        cover.setdefault((int(t[0]), int(t[1])), []).append((int(t[2]), int(t[3]), int(t[4]), int(t[5]),
+                                                             int(t[6]), int(t[7])))
+    assert set(cover) == {(0, 0), (0, 1), (1, 0), (2, 0), (2, 1), (2, 2), (2, 3), (2, 4), (3, 0)}
+    for (j, sb), parts in cover.items():
+        parts.sort()
+        npar = 2541 if kind[j] else 101
+        assert parts[0][0] == 0 and parts[-1][1] == npar
+        assert all(parts[i][1] == parts[i + 1][0] for i in range(len(parts) - 1))
+        assert all(p[4] == len(parts) for p in parts)
+        assert sorted(p[3] for p in parts) == list(range(len(parts)))
+        if len(parts) > 1:
+            assert len({p[2] for p in parts}) == 1 and parts[0][2] >= 0
+    assert ng == 1 * 5 + 1 * 1 and npart == 6 * 10
+    # the CRS tiles (cost ~ 64 x 256 x traces) come before the CMP ones
+    assert tiles[0][0] in (1, 2)
+
+
+def test_batch_plan_rejects_bad_input(semb):
+    import numpy as np
+    with pytest.raises(semb.SembError):
+        semb.batch_plan(np.array([2], np.int32), np.array([0], np.int32), np.array([0, 1], np.int32),
+                        np.array([0], np.int32), np.array([10], np.int32), np.array([0, 1], np.int32), 5, 5)
+    with pytest.raises(semb.SembError):
+        semb.batch_plan(np.array([0], np.int32), np.array([3], np.int32), np.array([0, 1], np.int32),
+                        np.array([0], np.int32), np.array([10], np.int32), np.array([0, 1], np.int32), 5, 5)

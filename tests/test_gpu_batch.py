@@ -1,0 +1,147 @@
+"""GPU tests of the batched scan (mixed CMP/CRS jobs, uneven fold and length,
+one persistent launch): it must equal the per-kind scans, match the oracle on
+sampled rows, and replay identically from a captured HIP graph."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1907_11678_amd as semb
+    semb.lib()
+    torch.cuda.set_device(0)
+    oracle.set_fragility(gu.FRAGILE_TAU, gu.FRAGILE_T_REL)
+    yield
+    oracle.set_fragility(*oracle.FRAGILE_DEFAULT)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+class Batch:
+    """A batch on the device, with its plan, workspace and outputs."""
+
+    def __init__(self, bw: synth.BatchWorkload, split_params: int = 256):
+        import torch
+        import paper_1907_11678_amd as semb
+        self.bw = bw
+        gs, jobs = bw.gathers, bw.jobs
+        self.dg, self.dj = gu.device_inputs(gs, jobs)
+        self.kind = torch.from_numpy(bw.kind).cuda()
+        tiles, self.ng, self.np = semb.batch_plan(bw.kind, jobs.central, jobs.apert_ptr, jobs.apert_gather,
+                                                  gs.ns, gs.trace_ptr, bw.grid_cmp.n, bw.grid_crs.n,
+                                                  split_params)
+        self.ntiles = tiles.shape[0]
+        self.tiles = torch.from_numpy(tiles).cuda()
+        self.ws = semb.alloc_batch_workspace(self.dg.nsamples, bw.w_cmp, bw.w_crs, self.ng, self.np)
+        self.qc = torch.from_numpy(bw.grid_cmp.q).cuda()
+        self.A, self.B, self.qr = (torch.from_numpy(x).cuda() for x in (bw.grid_crs.A, bw.grid_crs.B,
+                                                                           bw.grid_crs.q))
+        n = jobs.n_out
+        self.best = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+        self.sb = torch.full((n,), float("nan"), device="cuda")
+        self.st = torch.full((n,), float("nan"), device="cuda")
+
+    def run(self, stream=None):
+        import paper_1907_11678_amd as semb
+        semb.scan_batch(self.dg, self.dj, self.kind, self.qc, self.bw.w_cmp, self.A, self.B, self.qr,
+                        self.bw.w_crs, self.tiles, self.ng, self.np, self.best, self.sb, self.st, self.ws,
+                        stream=stream)
+
+    def outputs(self):
+        return (self.best.cpu().numpy(), self.sb.cpu().numpy().astype(np.float64),
+                self.st.cpu().numpy().astype(np.float64))
+
+
+def _kind_rows(bw, kind):
+    rows = []
+    for j in np.nonzero(bw.kind == kind)[0]:
+        o = int(bw.jobs.out_off[j])
+        rows.append(np.arange(o, o + int(bw.gathers.ns[bw.jobs.central[j]])))
+    return np.concatenate(rows) if rows else np.zeros(0, np.int64)
+
+
+@pytest.mark.parametrize("split", [256, 4096])
+def test_batch_equals_per_kind_scans(split):
+    """A 40-gather stretch of the batched line (uneven fold 8..120 and length
+    500..2000): the batch must reproduce cmp_scan on its CMP jobs and crs_scan
+    on its CRS jobs exactly (same per-cell sums in the same order)."""
+    import torch
+    bw = synth.batched_line(ids=range(2000, 2040))
+    b = Batch(bw, split)
+    b.run()
+    torch.cuda.synchronize()
+    best, sb, st = b.outputs()
+    for kind, grid, w in ((0, bw.grid_cmp, bw.w_cmp), (1, bw.grid_crs, bw.w_crs)):
+        sub = bw.subset(kind)
+        ref = gu.run_scan("cmp" if kind == 0 else "crs", bw.gathers, sub, grid, w, dg=b.dg,
+                          dj=gu.device_inputs(bw.gathers, sub)[1])
+        rows = _kind_rows(bw, kind)
+        assert np.array_equal(best[rows], ref[0][rows]), kind
+        assert np.array_equal(sb[rows], ref[1][rows]), kind
+        assert np.array_equal(st[rows], ref[2][rows]), kind
+    _say("batch == per-kind scans", b.ntiles, "tiles", b.ng, "groups")
+
+
+def test_batch_matches_oracle_on_sampled_rows():
+    import torch
+    bw = synth.batched_line(ids=range(600, 624))
+    b = Batch(bw)
+    b.run()
+    torch.cuda.synchronize()
+    best, sb, st = b.outputs()
+    rng = np.random.default_rng(4)
+    for kind, grid, w, nrow in ((0, bw.grid_cmp, bw.w_cmp, 48), (1, bw.grid_crs, bw.w_crs, 16)):
+        sub = bw.subset(kind)
+        pick = rng.integers(0, sub.njobs, nrow)
+        rj = pick.astype(np.int32)
+        rs = np.array([rng.integers(0, int(bw.gathers.ns[sub.central[j]])) for j in pick], np.int32)
+        ref = oracle.scan_rows("cmp" if kind == 0 else "crs", bw.gathers, sub, grid, w, rj, rs)
+        rows = sub.out_off[rj] + rs
+        _say("batch vs oracle", kind, gu.compare(f"batch kind {kind}", (best, sb, st, None), ref,
+                                                 gu.sample_scale(bw.gathers, sub), rows))
+
+
+def test_batch_graph_replay():
+    """Capture the batch (energy planes, counter reset, persistent kernel) in a
+    HIP graph; replay it three times with eager work in between and check
+    every replay against the eager result."""
+    import torch
+    bw = synth.batched_line(ids=range(3000, 3030))
+    b = Batch(bw)
+    b.run()
+    torch.cuda.synchronize()
+    eager = b.outputs()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.run(stream=s)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        b.run(stream=s)
+    for k in range(3):
+        b.best.fill_(-7)
+        b.sb.fill_(float("nan"))
+        b.st.fill_(float("nan"))
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = b.outputs()
+        for a_, e_ in zip(got, eager):
+            assert np.array_equal(a_, e_), f"replay {k} differs"
+        del junk
