@@ -161,6 +161,38 @@ semb_status semblance_grad(const semb_gathers *g, const semb_jobs *jobs, int32_t
                            float *g_samples, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Continuous refinement of coarse picks with the backward pass.
+ * ------------------------------------------------------------------------- */
+typedef struct semb_refine_opts {
+    int32_t steps;    /* ascent steps, >= 0                                        */
+    float eta0;       /* initial step length in normalised units (grid cells), >= 0 */
+    float scale[3];   /* unit of the normalised coordinates per component (A, B, q),
+                         e.g. the coarse grid spacing                              */
+    float lo[3];      /* the parameters stay inside [lo, hi] per component         */
+    float hi[3];
+} semb_refine_opts;
+
+/* Gradient-ascent refinement of each output row's parameter theta[row] =
+ * (A, B, q) (FP32 [n_out][3], read and overwritten; CMP keeps A = B = 0).  In
+ * coordinates u = theta / scale each step moves u a distance eta along the
+ * ascent direction dS/du / |dS/du| (dS/dtheta as in semblance_grad), clamps
+ * to [lo, hi], and keeps the step only if S increases (eta then grows by
+ * 1.25); otherwise eta halves.  Writes the final S and stack to s_out,
+ * stack_out [n_out].  Rows are independent; the whole loop runs on the device
+ * in one launch. */
+semb_status semb_refine(const semb_gathers *g, const semb_jobs *jobs, int32_t kind, float *theta,
+                        const semb_refine_opts *o, int32_t w, float *s_out, float *stack_out,
+                        hipStream_t stream);
+
+/* theta[row] = (A[iA], B[iB], q[iq]) for the flat index best[row] =
+ * (iA * nB + iB) * nq + iq (A, B may be NULL: 0 is written; indices outside
+ * the grid are clamped).  Turns a scan's picks into refine's starting point
+ * without a host round trip. */
+semb_status semb_theta_from_best(const int32_t *best, int64_t n_out, const float *A, int32_t nA,
+                                 const float *B, int32_t nB, const float *q, int32_t nq, float *theta,
+                                 hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Batched scan: CMP and CRS jobs of uneven fold and length in ONE persistent
  * launch (the paper processes CDPs as independent tasks, section 3.5; here
  * they are balanced across the GPU instead of across core groups).

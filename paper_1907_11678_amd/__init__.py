@@ -53,6 +53,11 @@ class COutputs(C.Structure):
                 ("panel", C.c_void_p)]
 
 
+class CRefineOpts(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("eta0", C.c_float), ("scale", C.c_float * 3), ("lo", C.c_float * 3),
+                ("hi", C.c_float * 3)]
+
+
 class CTile(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("job", "sblk", "p_begin", "p_end", "group", "split", "nsplit",
                                           "part_base")]
@@ -97,6 +102,10 @@ def lib():
         L.semb_batch_workspace_bytes.restype = C.c_size_t
         L.scan_batch.argtypes = [P, P, P, P, i64, i32, i32, P, P, C.c_size_t, P]
         L.scan_batch.restype = C.c_int
+        L.semb_refine.argtypes = [P, P, i32, P, P, i32, P, P, P]
+        L.semb_refine.restype = C.c_int
+        L.semb_theta_from_best.argtypes = [P, i64, P, i32, P, i32, P, i32, P, P]
+        L.semb_theta_from_best.restype = C.c_int
         L.semb_last_error.restype = C.c_char_p
         L.semb_version.restype = C.c_char_p
         _lib = L
@@ -350,3 +359,73 @@ def scan_batch(g: DeviceGathers, jobs: DeviceJobs, kind, q_cmp, w_cmp: int, A, B
     _check(lib().scan_batch(C.byref(gs), C.byref(js), C.byref(b), _typed(tiles, torch.int32, "tiles"),
                             int(tiles.shape[0]), int(ngroups), int(nparts), C.byref(out), _ptr(ws),
                             int(ws.numel() * ws.element_size()), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# refinement and autograd
+# ---------------------------------------------------------------------------
+def theta_from_best(best, q, theta, A=None, B=None, stream=None):
+    """theta[row] = grid parameter (A, B, q) of the flat index best[row]."""
+    import torch
+    _check(lib().semb_theta_from_best(_typed(best, torch.int32, "best"), int(best.numel()),
+                                      _typed(A, torch.float32, "A"), int(A.numel()) if A is not None else 1,
+                                      _typed(B, torch.float32, "B"), int(B.numel()) if B is not None else 1,
+                                      _typed(q, torch.float32, "q"), int(q.numel()),
+                                      _typed(theta, torch.float32, "theta"), _stream(stream)))
+
+
+def refine(g: DeviceGathers, jobs: DeviceJobs, kind: int, theta, w: int, s_out, stack_out, steps: int = 8,
+           eta0: float = 0.5, scale=(1.0, 1.0, 1.0), lo=(-1e30, -1e30, -1e30), hi=(1e30, 1e30, 1e30),
+           stream=None):
+    """Gradient-ascent refinement of theta [n_out, 3] in place (see semb_refine)."""
+    import torch
+    gs, js = g.cstruct(), jobs.cstruct()
+    o = CRefineOpts(int(steps), float(eta0), (C.c_float * 3)(*scale), (C.c_float * 3)(*lo),
+                    (C.c_float * 3)(*hi))
+    _check(lib().semb_refine(C.byref(gs), C.byref(js), int(kind), _typed(theta, torch.float32, "theta"),
+                             C.byref(o), int(w), _typed(s_out, torch.float32, "s_out"),
+                             _typed(stack_out, torch.float32, "stack_out"), _stream(stream)))
+
+
+def _semblance_at_class():
+    import torch
+
+    class SemblanceAt(torch.autograd.Function):
+        """S(theta) per output row: forward = `stack`, backward = `semblance_grad`.
+
+        Inputs: samples (the tensor g.samples holds, so its gradient can be
+        requested), theta [n_out, 3]; g, jobs, kind and w are constants."""
+
+        @staticmethod
+        def forward(ctx, samples, theta, g, jobs, kind, w):
+            if samples.data_ptr() != g.samples.data_ptr():
+                raise ValueError("samples must be the tensor the gathers were uploaded with")
+            theta = theta.contiguous()
+            S = torch.empty(jobs.n_out, dtype=torch.float32, device=theta.device)
+            st = torch.empty_like(S)
+            stack(g, jobs, kind, theta, w, S, st)
+            ctx.save_for_backward(theta)
+            ctx.g, ctx.jobs, ctx.kind, ctx.w = g, jobs, kind, w
+            ctx.mark_non_differentiable(st)
+            return S, st
+
+        @staticmethod
+        def backward(ctx, gS, _gst):
+            (theta,) = ctx.saved_tensors
+            g_theta = torch.empty_like(theta)
+            g_samples = torch.zeros_like(ctx.g.samples) if ctx.needs_input_grad[0] else None
+            semblance_grad(ctx.g, ctx.jobs, ctx.kind, theta, gS.contiguous().float(), ctx.w, g_theta, g_samples)
+            return g_samples, g_theta, None, None, None, None
+
+    return SemblanceAt
+
+
+_SemblanceAt = None
+
+
+def semblance_at(samples, theta, g: DeviceGathers, jobs: DeviceJobs, kind: int, w: int):
+    """Differentiable S (and non-differentiable stack) at theta; see SemblanceAt."""
+    global _SemblanceAt
+    if _SemblanceAt is None:
+        _SemblanceAt = _semblance_at_class()
+    return _SemblanceAt.apply(samples, theta, g, jobs, kind, w)

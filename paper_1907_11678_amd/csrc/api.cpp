@@ -413,6 +413,64 @@ semb_status semblance_grad(const semb_gathers *g, const semb_jobs *jobs, int32_t
     return point_common(true, g, jobs, kind, theta, g_s, w, nullptr, nullptr, g_theta, g_samples, stream);
 }
 
+semb_status semb_refine(const semb_gathers *g, const semb_jobs *jobs, int32_t kind, float *theta,
+                        const semb_refine_opts *o, int32_t w, float *s_out, float *stack_out, hipStream_t stream)
+{
+    if (kind != SEMB_KIND_CMP && kind != SEMB_KIND_CRS) return fail(SEMB_EINVAL, "kind must be CMP or CRS");
+    const bool crs = kind == SEMB_KIND_CRS;
+    TRY(check_gathers(g, crs));
+    TRY(check_jobs(jobs, crs, g));
+    TRY(check_w(w));
+    if (!o) return fail(SEMB_EINVAL, "refine options are NULL");
+    if (o->steps < 0 || !(o->eta0 >= 0.f) || !isfinite(o->eta0))
+        return fail(SEMB_EINVAL, "steps must be >= 0 and eta0 finite and >= 0");
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(o->scale[k]) || !(o->lo[k] <= o->hi[k]))
+            return fail(SEMB_EINVAL, "scale must be finite and lo <= hi for every component");
+    if (jobs->njobs == 0) return SEMB_OK;
+    if (!theta || !s_out || !stack_out) return fail(SEMB_EINVAL, "theta, s_out and stack_out are required");
+    semb::PointArgs a{};
+    a.samples = g->samples;
+    a.sample_off = g->sample_off;
+    a.trace_ptr = g->trace_ptr;
+    a.ns = g->ns;
+    a.half_offset = g->half_offset;
+    a.midpoint = g->midpoint;
+    a.central_x = g->central_x;
+    a.dt = g->dt;
+    a.central = jobs->central;
+    a.apert_ptr = crs ? jobs->apert_ptr : nullptr;
+    a.apert_gather = crs ? jobs->apert_gather : nullptr;
+    a.out_off = jobs->out_off;
+    a.njobs = jobs->njobs;
+    a.n_sblk = (g->ns_max + 63) / 64;
+    a.theta = theta;
+    a.s_out = s_out;
+    a.stack_out = stack_out;
+    a.w = w;
+    semb::RefineArgs r{};
+    r.theta = theta;
+    r.steps = o->steps;
+    r.eta0 = o->eta0;
+    for (int k = 0; k < 3; ++k) {
+        r.scale[k] = o->scale[k];
+        r.lo[k] = o->lo[k];
+        r.hi[k] = o->hi[k];
+    }
+    return hip_status(semb::launch_refine(kind, a, r, stream), "semb_refine launch");
+}
+
+semb_status semb_theta_from_best(const int32_t *best, int64_t n_out, const float *A, int32_t nA, const float *B,
+                                 int32_t nB, const float *q, int32_t nq, float *theta, hipStream_t stream)
+{
+    if (n_out < 0) return fail(SEMB_EINVAL, "n_out must be >= 0");
+    if (n_out == 0) return SEMB_OK;
+    if (!best || !q || nq < 1 || !theta) return fail(SEMB_EINVAL, "best, q and theta are required, nq >= 1");
+    if ((A && nA < 1) || (B && nB < 1)) return fail(SEMB_EINVAL, "nA and nB must be >= 1");
+    return hip_status(semb::launch_theta_from_best(best, n_out, A, A ? nA : 1, B, B ? nB : 1, q, nq, theta, stream),
+                      "semb_theta_from_best launch");
+}
+
 const char *semb_last_error(void) { return g_last_error.c_str(); }
 
 const char *semb_version(void) { return "semb-mi355x 0.1 (gfx950)"; }

@@ -103,6 +103,16 @@ struct PointArgs {
     int32_t w;
 };
 
+// Options of the gradient-ascent refinement (see semb_refine).
+struct RefineArgs {
+    float *theta;  // [n_out][3], read and overwritten
+    int32_t steps;
+    float eta0;
+    float scale[3];
+    float lo[3];
+    float hi[3];
+};
+
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_window_energy(const float *samples, const int64_t *sample_off,
                                 const int32_t *trace_ptr, const int32_t *ns, int32_t ngathers,
@@ -112,5 +122,8 @@ hipError_t launch_scan(int kind, const ScanArgs &a, hipStream_t stream);
 hipError_t launch_batch(const BatchArgs &a, int ngroups, hipStream_t stream);
 hipError_t launch_point(int kind, const PointArgs &a, hipStream_t stream);
 hipError_t launch_grad(int kind, const PointArgs &a, hipStream_t stream);
+hipError_t launch_refine(int kind, const PointArgs &a, const RefineArgs &o, hipStream_t stream);
+hipError_t launch_theta_from_best(const int32_t *best, int64_t n, const float *A, int nA, const float *B, int nB,
+                                  const float *q, int nq, float *theta, hipStream_t stream);
 
 }  // namespace semb

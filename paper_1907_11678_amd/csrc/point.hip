@@ -63,46 +63,69 @@ __device__ __forceinline__ Isect intersect(int s, double A, double B, double q, 
     return r;
 }
 
-template <int KIND, int W, bool GRAD>
-__global__ void __launch_bounds__(WAVE)
-point_kernel(PointArgs a)
+// The rows of a job: its central gather, aperture and output row offset.
+struct RowCtx {
+    int c, k0, k1;
+    const int32_t *ag;  // aperture gathers, or NULL for the central alone
+    double xc, inv_dt;
+};
+
+template <int KIND>
+__device__ __forceinline__ RowCtx row_ctx(const PointArgs &a, int job)
 {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int job = tile / a.n_sblk;
-    const int sblk = tile - job * a.n_sblk;
-    if (job >= a.njobs) return;
-    const int c = a.central[job];
-    const int nsc = a.ns[c];
-    const int s = sblk * WAVE + (int)threadIdx.x;
-    if (s >= nsc) return;
-
-    const int64_t row = a.out_off[job] + s;
-    const double inv_dt = 1.0 / (double)a.dt;
-    const double A = (KIND == SEMB_KIND_CRS) ? (double)a.theta[3 * row + 0] : 0.0;
-    const double B = (KIND == SEMB_KIND_CRS) ? (double)a.theta[3 * row + 1] : 0.0;
-    const double q = (double)a.theta[3 * row + 2];
-    const double xc = (KIND == SEMB_KIND_CRS) ? (double)a.central_x[c] : 0.0;
-
-    int k0 = 0, k1 = 1;
+    RowCtx r;
+    r.c = a.central[job];
+    r.k0 = 0;
+    r.k1 = 1;
+    r.ag = nullptr;
     if (KIND == SEMB_KIND_CRS && a.apert_ptr != nullptr) {
-        k0 = a.apert_ptr[job];
-        k1 = a.apert_ptr[job + 1];
+        r.k0 = a.apert_ptr[job];
+        r.k1 = a.apert_ptr[job + 1];
+        r.ag = a.apert_gather;
     }
+    r.xc = (KIND == SEMB_KIND_CRS) ? (double)a.central_x[r.c] : 0.0;
+    r.inv_dt = 1.0 / (double)a.dt;
+    return r;
+}
 
+// Semblance sums at one parameter: U[W], D, M (pass 1 of Eq. (1)).
+template <int W>
+struct Sums {
     float U[W];
+    float D, M;
+    __device__ float S() const
+    {
+        float N = 0.f;
 #pragma unroll
-    for (int j = 0; j < W; ++j) U[j] = 0.f;
-    float D = 0.f, M = 0.f;
+        for (int j = 0; j < W; ++j) N = fmaf(U[j], U[j], N);
+        return (M > 0.f && D > 0.f) ? N / (M * D) : 0.f;
+    }
+    __device__ float stack() const
+    {
+        float L = 0.f;
+#pragma unroll
+        for (int j = 0; j < W; ++j) L += U[j];
+        return (M > 0.f) ? L / (M * (float)W) : 0.f;
+    }
+};
 
-    // ---- pass 1: U, D, M ---------------------------------------------------
-    for (int k = k0; k < k1; ++k) {
-        const int g = (KIND == SEMB_KIND_CRS && a.apert_ptr != nullptr) ? a.apert_gather[k] : c;
+template <int KIND, int W>
+__device__ __forceinline__ Sums<W> sums_at(const PointArgs &a, const RowCtx &r, int s, double A, double B,
+                                           double q)
+{
+    Sums<W> t;
+#pragma unroll
+    for (int j = 0; j < W; ++j) t.U[j] = 0.f;
+    t.D = 0.f;
+    t.M = 0.f;
+    for (int k = r.k0; k < r.k1; ++k) {
+        const int g = r.ag ? r.ag[k] : r.c;
         const int nsg = a.ns[g];
         const int tb = a.trace_ptr[g], te = a.trace_ptr[g + 1];
         for (int i = tb; i < te; ++i) {
             // displacement rounded to FP32 as the scan's trace table holds it
-            const float dmf = (KIND == SEMB_KIND_CRS) ? (float)((double)a.midpoint[i] - xc) : 0.f;
-            const Isect hit = intersect<KIND, W>(s, A, B, q, a.half_offset[i], dmf, inv_dt, nsg);
+            const float dmf = (KIND == SEMB_KIND_CRS) ? (float)((double)a.midpoint[i] - r.xc) : 0.f;
+            const Isect hit = intersect<KIND, W>(s, A, B, q, a.half_offset[i], dmf, r.inv_dt, nsg);
             if (!hit.valid) continue;
             const float *f = a.samples + a.sample_off[g] + (int64_t)(i - tb) * nsg + hit.a;
             float prev = f[0];
@@ -110,77 +133,174 @@ point_kernel(PointArgs a)
             for (int j = 0; j < W; ++j) {
                 const float nxt = f[j + 1];
                 const float v = fmaf(hit.x, nxt - prev, prev);
-                U[j] += v;
-                D = fmaf(v, v, D);
+                t.U[j] += v;
+                t.D = fmaf(v, v, t.D);
                 prev = nxt;
             }
-            M += 1.f;
+            t.M += 1.f;
         }
     }
-    float N = 0.f, L = 0.f;
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-        N = fmaf(U[j], U[j], N);
-        L += U[j];
-    }
-    const bool live = (M > 0.f && D > 0.f);
-    const float S = live ? N / (M * D) : 0.f;
+    return t;
+}
 
-    if (!GRAD) {
-        a.s_out[row] = S;
-        a.stack_out[row] = (M > 0.f) ? L / (M * (float)W) : 0.f;
-        return;
-    }
-
-    // ---- pass 2: dS/dtau per trace, dS/dsample scattered -------------------
-    const float gs = a.g_s[row];
-    float gA = 0.f, gB = 0.f, gq = 0.f;
-    if (live && gs != 0.f) {
-        const float inv_MD = 1.f / (M * D);
-        const float SM = S * M;
-        const float dtf = a.dt;
-        const float t0 = (float)s * dtf;
-        for (int k = k0; k < k1; ++k) {
-            const int g = (KIND == SEMB_KIND_CRS && a.apert_ptr != nullptr) ? a.apert_gather[k] : c;
-            const int nsg = a.ns[g];
-            const int tb = a.trace_ptr[g], te = a.trace_ptr[g + 1];
-            for (int i = tb; i < te; ++i) {
-                const float dmf = (KIND == SEMB_KIND_CRS) ? (float)((double)a.midpoint[i] - xc) : 0.f;
-                const Isect hit = intersect<KIND, W>(s, A, B, q, a.half_offset[i], dmf, inv_dt, nsg);
-                if (!hit.valid) continue;
-                const int64_t base = a.sample_off[g] + (int64_t)(i - tb) * nsg + hit.a;
-                const float *f = a.samples + base;
-                float dS_dtau = 0.f;
-                float carry = 0.f;  // x * dS/dv of the previous window sample
-                float prev = f[0];
+// Pass 2: gs * dS/d(A, B, q) at the parameter whose sums are t (S > 0 needs
+// M > 0 and D > 0), scattering gs * dS/dsample into g_samples if not NULL.
+template <int KIND, int W>
+__device__ __forceinline__ void grad_at(const PointArgs &a, const RowCtx &r, int s, double A, double B, double q,
+                                        const Sums<W> &t, float gs, float *g_samples, float &gA, float &gB,
+                                        float &gq)
+{
+    gA = gB = gq = 0.f;
+    if (!(t.M > 0.f && t.D > 0.f) || gs == 0.f) return;
+    const float S = t.S();
+    const float inv_MD = 1.f / (t.M * t.D);
+    const float SM = S * t.M;
+    const float dtf = a.dt;
+    const float t0 = (float)s * dtf;
+    for (int k = r.k0; k < r.k1; ++k) {
+        const int g = r.ag ? r.ag[k] : r.c;
+        const int nsg = a.ns[g];
+        const int tb = a.trace_ptr[g], te = a.trace_ptr[g + 1];
+        for (int i = tb; i < te; ++i) {
+            const float dmf = (KIND == SEMB_KIND_CRS) ? (float)((double)a.midpoint[i] - r.xc) : 0.f;
+            const Isect hit = intersect<KIND, W>(s, A, B, q, a.half_offset[i], dmf, r.inv_dt, nsg);
+            if (!hit.valid) continue;
+            const int64_t base = a.sample_off[g] + (int64_t)(i - tb) * nsg + hit.a;
+            const float *f = a.samples + base;
+            float dS_dtau = 0.f;
+            float carry = 0.f;  // x * dS/dv of the previous window sample
+            float prev = f[0];
 #pragma unroll
-                for (int j = 0; j < W; ++j) {
-                    const float nxt = f[j + 1];
-                    const float slope = nxt - prev;
-                    const float v = fmaf(hit.x, slope, prev);
-                    const float dSdv = 2.f * (U[j] - SM * v) * inv_MD;
-                    dS_dtau = fmaf(dSdv, slope, dS_dtau);
-                    if (a.g_samples) atomicAdd(a.g_samples + base + j, gs * ((1.f - hit.x) * dSdv + carry));
-                    carry = hit.x * dSdv;
-                    prev = nxt;
+            for (int j = 0; j < W; ++j) {
+                const float nxt = f[j + 1];
+                const float slope = nxt - prev;
+                const float v = fmaf(hit.x, slope, prev);
+                const float dSdv = 2.f * (t.U[j] - SM * v) * inv_MD;
+                dS_dtau = fmaf(dSdv, slope, dS_dtau);
+                if (g_samples) atomicAdd(g_samples + base + j, gs * ((1.f - hit.x) * dSdv + carry));
+                carry = hit.x * dSdv;
+                prev = nxt;
+            }
+            if (g_samples) atomicAdd(g_samples + base + W, gs * carry);
+            if (hit.tau > 0.f) {
+                // dtau/dT = 1 / (2 dt sqrt(T)) with sqrt(T) = tau * dt
+                const float k_t = dS_dtau / (2.f * hit.tau * dtf * dtf);
+                const float h = a.half_offset[i];
+                if (KIND == SEMB_KIND_CRS) {
+                    gA = fmaf(k_t, 4.f * dmf * (t0 + 2.f * (float)A * dmf), gA);
+                    gB = fmaf(k_t, 2.f * t0 * dmf * dmf, gB);
                 }
-                if (a.g_samples) atomicAdd(a.g_samples + base + W, gs * carry);
-                if (hit.tau > 0.f) {
-                    // dtau/dT = 1 / (2 dt sqrt(T)) with sqrt(T) = tau * dt
-                    const float k_t = dS_dtau / (2.f * hit.tau * dtf * dtf);
-                    const float h = a.half_offset[i];
-                    if (KIND == SEMB_KIND_CRS) {
-                        gA = fmaf(k_t, 4.f * dmf * (t0 + 2.f * (float)A * dmf), gA);
-                        gB = fmaf(k_t, 2.f * t0 * dmf * dmf, gB);
-                    }
-                    gq = fmaf(k_t, h * h, gq);
-                }
+                gq = fmaf(k_t, h * h, gq);
             }
         }
     }
-    a.g_theta[3 * row + 0] = gs * gA;
-    a.g_theta[3 * row + 1] = gs * gB;
-    a.g_theta[3 * row + 2] = gs * gq;
+    gA *= gs;
+    gB *= gs;
+    gq *= gs;
+}
+
+// One lane per output sample: the row of lane l of the workgroup, or -1.
+template <int KIND>
+__device__ __forceinline__ int64_t my_row(const PointArgs &a, int &job, int &s)
+{
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    job = tile / a.n_sblk;
+    const int sblk = tile - job * a.n_sblk;
+    if (job >= a.njobs) return -1;
+    s = sblk * WAVE + (int)threadIdx.x;
+    if (s >= a.ns[a.central[job]]) return -1;
+    return a.out_off[job] + s;
+}
+
+template <int KIND, int W, bool GRAD>
+__global__ void __launch_bounds__(WAVE)
+point_kernel(PointArgs a)
+{
+    int job, s;
+    const int64_t row = my_row<KIND>(a, job, s);
+    if (row < 0) return;
+    const RowCtx r = row_ctx<KIND>(a, job);
+    const double A = (KIND == SEMB_KIND_CRS) ? (double)a.theta[3 * row + 0] : 0.0;
+    const double B = (KIND == SEMB_KIND_CRS) ? (double)a.theta[3 * row + 1] : 0.0;
+    const double q = (double)a.theta[3 * row + 2];
+    const Sums<W> t = sums_at<KIND, W>(a, r, s, A, B, q);
+    if (!GRAD) {
+        a.s_out[row] = t.S();
+        a.stack_out[row] = t.stack();
+        return;
+    }
+    float gA, gB, gq;
+    grad_at<KIND, W>(a, r, s, A, B, q, t, a.g_s[row], a.g_samples, gA, gB, gq);
+    a.g_theta[3 * row + 0] = gA;
+    a.g_theta[3 * row + 1] = gB;
+    a.g_theta[3 * row + 2] = gq;
+}
+
+// Gradient-ascent refinement of every output sample's parameter, all steps in
+// one kernel (rows are independent).  In coordinates normalised by the grid
+// spacing (u = theta / scale) each step moves u a distance eta along the
+// ascent direction dS/du / |dS/du| (theta += eta * scale^2 * g / |scale * g|),
+// clamped to [lo, hi]; a step is kept only if S increases (then eta grows by
+// 1.25), otherwise eta halves.  Writes the refined theta, its S and stack.
+template <int KIND, int W>
+__global__ void __launch_bounds__(WAVE)
+refine_kernel(PointArgs a, RefineArgs o)
+{
+    int job, s;
+    const int64_t row = my_row<KIND>(a, job, s);
+    if (row < 0) return;
+    const RowCtx r = row_ctx<KIND>(a, job);
+    float th[3] = {o.theta[3 * row + 0], o.theta[3 * row + 1], o.theta[3 * row + 2]};
+    if (KIND == SEMB_KIND_CMP) th[0] = th[1] = 0.f;
+    Sums<W> cur = sums_at<KIND, W>(a, r, s, th[0], th[1], th[2]);
+    float S = cur.S();
+    float eta = o.eta0;
+    for (int it = 0; it < o.steps; ++it) {
+        float g[3];
+        grad_at<KIND, W>(a, r, s, th[0], th[1], th[2], cur, 1.f, nullptr, g[0], g[1], g[2]);
+        float gu[3], nrm = 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            gu[k] = o.scale[k] * g[k];  // dS/du
+            nrm = fmaf(gu[k], gu[k], nrm);
+        }
+        if (!(nrm > 0.f)) break;  // flat (or S = 0): nothing to climb
+        const float inv = eta * rsqrtf(nrm);
+        float tr[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) tr[k] = fminf(fmaxf(fmaf(o.scale[k] * inv, gu[k], th[k]), o.lo[k]), o.hi[k]);
+        if (KIND == SEMB_KIND_CMP) tr[0] = tr[1] = 0.f;
+        const Sums<W> nxt = sums_at<KIND, W>(a, r, s, tr[0], tr[1], tr[2]);
+        const float Sn = nxt.S();
+        if (Sn > S) {
+            S = Sn;
+            cur = nxt;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) th[k] = tr[k];
+            eta *= 1.25f;
+        } else {
+            eta *= 0.5f;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) o.theta[3 * row + k] = th[k];
+    a.s_out[row] = S;
+    a.stack_out[row] = cur.stack();
+}
+
+// theta[row] = (A, B, q) of the flat index best[row] ((iA * nB + iB) * nq + iq).
+__global__ void theta_from_best_kernel(const int32_t *best, int64_t n, const float *A, int nA, const float *B, int nB,
+                                       const float *q, int nq, float *theta)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int b = best[i];
+        const int npar = nA * nB * nq;
+        b = b < 0 ? 0 : (b >= npar ? npar - 1 : b);
+        const int iq = b % nq, rest = b / nq;
+        theta[3 * i + 0] = A ? A[rest / nB] : 0.f;
+        theta[3 * i + 1] = B ? B[rest % nB] : 0.f;
+        theta[3 * i + 2] = q[iq];
+    }
 }
 
 template <int KIND, bool GRAD, int W>
@@ -216,7 +336,55 @@ hipError_t launch_p(const PointArgs &a, hipStream_t stream)
     }
 }
 
+template <int KIND, int W>
+hipError_t launch_rw(const PointArgs &a, const RefineArgs &o, hipStream_t stream)
+{
+    const long long nblk = (long long)a.njobs * a.n_sblk;
+    if (nblk == 0) return hipSuccess;
+    hipLaunchKernelGGL((refine_kernel<KIND, W>), dim3((unsigned)nblk), dim3(WAVE), 0, stream, a, o);
+    return hipGetLastError();
+}
+
+template <int KIND>
+hipError_t launch_r(const PointArgs &a, const RefineArgs &o, hipStream_t stream)
+{
+    switch (a.w) {
+    case 1: return launch_rw<KIND, 1>(a, o, stream);
+    case 3: return launch_rw<KIND, 3>(a, o, stream);
+    case 5: return launch_rw<KIND, 5>(a, o, stream);
+    case 7: return launch_rw<KIND, 7>(a, o, stream);
+    case 9: return launch_rw<KIND, 9>(a, o, stream);
+    case 11: return launch_rw<KIND, 11>(a, o, stream);
+    case 13: return launch_rw<KIND, 13>(a, o, stream);
+    case 15: return launch_rw<KIND, 15>(a, o, stream);
+    case 17: return launch_rw<KIND, 17>(a, o, stream);
+    case 19: return launch_rw<KIND, 19>(a, o, stream);
+    case 21: return launch_rw<KIND, 21>(a, o, stream);
+    case 23: return launch_rw<KIND, 23>(a, o, stream);
+    case 25: return launch_rw<KIND, 25>(a, o, stream);
+    case 27: return launch_rw<KIND, 27>(a, o, stream);
+    case 29: return launch_rw<KIND, 29>(a, o, stream);
+    case 31: return launch_rw<KIND, 31>(a, o, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_refine(int kind, const PointArgs &a, const RefineArgs &o, hipStream_t stream)
+{
+    return kind == SEMB_KIND_CMP ? launch_r<SEMB_KIND_CMP>(a, o, stream) : launch_r<SEMB_KIND_CRS>(a, o, stream);
+}
+
+hipError_t launch_theta_from_best(const int32_t *best, int64_t n, const float *A, int nA, const float *B, int nB,
+                                  const float *q, int nq, float *theta, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const long long nb = (n + 255) / 256;
+    hipLaunchKernelGGL(theta_from_best_kernel, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, stream, best,
+                       n, A, nA, B, nB, q, nq, theta);
+    return hipGetLastError();
+}
 
 hipError_t launch_point(int kind, const PointArgs &a, hipStream_t stream)
 {

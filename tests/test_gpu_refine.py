@@ -1,0 +1,181 @@
+"""GPU tests of the continuous refinement: coarse CRS scan -> picks to
+parameters -> gradient ascent with the backward pass, and the autograd
+wrapper of stack / semblance_grad."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1907_11678_amd as semb
+    semb.lib()
+    torch.cuda.set_device(0)
+    oracle.set_fragility(gu.FRAGILE_TAU, gu.FRAGILE_T_REL)
+    yield
+    oracle.set_fragility(*oracle.FRAGILE_DEFAULT)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def coarse_scale_bounds(grid: synth.Grid):
+    """Normalising unit (one coarse grid cell) and box of each component."""
+    def cell(v):
+        v = np.asarray(v, np.float64)
+        return float((v.max() - v.min()) / max(v.size - 1, 1))
+    scale = (cell(grid.A), cell(grid.B), cell(grid.q))
+    lo = (float(grid.A.min()), float(grid.B.min()), float(grid.q.min()))
+    hi = (float(grid.A.max()), float(grid.B.max()), float(grid.q.max()))
+    return scale, lo, hi
+
+
+def test_theta_from_best_matches_grid():
+    import torch
+    import paper_1907_11678_amd as semb
+    grid = synth.crs_coarse_grid()
+    best = np.random.default_rng(0).integers(0, grid.n, 5000).astype(np.int32)
+    th = torch.empty((best.size, 3), device="cuda")
+    semb.theta_from_best(torch.from_numpy(best).cuda(), torch.from_numpy(grid.q).cuda(), th,
+                         A=torch.from_numpy(grid.A).cuda(), B=torch.from_numpy(grid.B).cuda())
+    torch.cuda.synchronize()
+    ref = oracle.theta_of(grid, best, "crs").astype(np.float32)
+    assert np.array_equal(th.cpu().numpy(), ref)
+
+
+class Refinement:
+    def __init__(self, wl, steps=8):
+        import torch
+        import paper_1907_11678_amd as semb
+        self.wl = wl
+        gs, jobs = wl.gathers, wl.jobs
+        self.dg, self.dj = gu.device_inputs(gs, jobs)
+        n = jobs.n_out
+        self.n = n
+        self.coarse = synth.crs_coarse_grid()
+        self.A, self.B, self.q = (torch.from_numpy(x).cuda() for x in (self.coarse.A, self.coarse.B, self.coarse.q))
+        self.best = torch.empty(n, dtype=torch.int32, device="cuda")
+        self.s0 = torch.empty(n, device="cuda")
+        self.st0 = torch.empty(n, device="cuda")
+        self.theta = torch.empty((n, 3), device="cuda")
+        self.S = torch.empty(n, device="cuda")
+        self.st = torch.empty(n, device="cuda")
+        self.ws = semb.alloc_workspace(self.dg.nsamples)
+        self.scale, self.lo, self.hi = coarse_scale_bounds(self.coarse)
+        self.steps = steps
+
+    def run(self, stream=None):
+        import paper_1907_11678_amd as semb
+        semb.crs_scan(self.dg, self.dj, self.A, self.B, self.q, self.wl.w, self.best, self.s0, self.st0, self.ws,
+                      stream=stream)
+        semb.theta_from_best(self.best, self.q, self.theta, A=self.A, B=self.B, stream=stream)
+        semb.refine(self.dg, self.dj, 1, self.theta, self.wl.w, self.S, self.st, steps=self.steps, eta0=0.5,
+                    scale=self.scale, lo=self.lo, hi=self.hi, stream=stream)
+
+
+def test_refinement_is_monotone_and_reports_its_semblance():
+    import torch
+    wl = synth.crs_line(centrals=[60, 61, 250, 400])
+    r = Refinement(wl)
+    r.run()
+    torch.cuda.synchronize()
+    s0 = r.s0.cpu().numpy().astype(np.float64)
+    S = r.S.cpu().numpy().astype(np.float64)
+    th = r.theta.cpu().numpy().astype(np.float64)
+    assert (S >= s0 - 1e-6).all(), "a step was kept that lowered S"
+    assert (th >= np.array(r.lo) - 1e-12).all() and (th <= np.array(r.hi) + 1e-12).all()
+    Sref, STref, M, fr = oracle.point("crs", wl.gathers, wl.jobs, th, wl.w)
+    ok = ~fr
+    assert np.abs(S - Sref)[ok].max() <= gu.S_TOL
+    scale = gu.sample_scale(wl.gathers, wl.jobs)
+    assert (np.abs(r.st.cpu().numpy() - STref) / scale)[ok].max() <= gu.STACK_TOL
+    gain = S - s0
+    _say(f"refinement: mean S coarse {s0.mean():.4f} -> refined {S.mean():.4f}; "
+         f"rows improved {(gain > 1e-6).mean():.3f}")
+    assert (gain > 1e-6).mean() > 0.5
+
+
+def test_refinement_reaches_the_fine_grid():
+    """Coarse 7x7x11 + 8 ascent steps against the exhaustive 21x21x41 scan."""
+    import torch
+    wl = synth.crs_line(centrals=[120, 121])
+    r = Refinement(wl)
+    r.run()
+    fine = gu.run_scan("crs", wl.gathers, wl.jobs, wl.grid, wl.w, dg=r.dg, dj=r.dj)
+    torch.cuda.synchronize()
+    S = r.S.cpu().numpy().astype(np.float64)
+    Sf = fine[1]
+    sel = Sf > 0.1
+    d = (S - Sf)[sel]
+    _say(f"refined - fine-grid S over {sel.sum()} rows: median {np.median(d):+.4f}, "
+         f"p5 {np.percentile(d, 5):+.4f}, >= -1e-4: {(d >= -1e-4).mean():.3f}")
+    assert np.median(d) > -0.02
+
+
+def test_refinement_graph_replay():
+    import torch
+    wl = synth.crs_line(centrals=[300])
+    r = Refinement(wl)
+    r.run()
+    torch.cuda.synchronize()
+    eager = (r.theta.cpu().numpy(), r.S.cpu().numpy(), r.st.cpu().numpy())
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        r.run(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        r.run(stream=s)
+    for k in range(3):
+        r.theta.fill_(0.0)
+        r.S.fill_(-1.0)
+        torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = (r.theta.cpu().numpy(), r.S.cpu().numpy(), r.st.cpu().numpy())
+        for a_, e_ in zip(got, eager):
+            assert np.array_equal(a_, e_), f"replay {k}"
+
+
+def test_autograd_wrapper_matches_oracle_gradient():
+    import torch
+    import paper_1907_11678_amd as semb
+    wl = synth.crs_line(centrals=[77])
+    gs, jobs = wl.gathers, wl.jobs
+    dg, dj = gu.device_inputs(gs, jobs)
+    rng = np.random.default_rng(3)
+    th = np.zeros((jobs.n_out, 3), np.float32)
+    th[:, 0] = rng.uniform(-4e-4, 4e-4, jobs.n_out)
+    th[:, 1] = rng.uniform(-8e-8, 8e-8, jobs.n_out)
+    th[:, 2] = 4.0 / rng.uniform(1500, 4500, jobs.n_out) ** 2
+    theta = torch.from_numpy(th).cuda().requires_grad_(True)
+    samples = dg.samples.requires_grad_(True)
+    S, st = semb.semblance_at(samples, theta, dg, dj, 1, wl.w)
+    weights = torch.from_numpy(rng.uniform(0.5, 1.5, jobs.n_out).astype(np.float32)).cuda()
+    (S * weights).sum().backward()
+    torch.cuda.synchronize()
+    gt_ref, gsm_ref = oracle.grad("crs", gs, jobs, th.astype(np.float64), weights.cpu().numpy().astype(np.float64),
+                                  wl.w)
+    S_ref, _, _, fr = oracle.point("crs", gs, jobs, th.astype(np.float64), wl.w)
+    assert np.abs(S.detach().cpu().numpy() - S_ref)[~fr].max() <= gu.S_TOL
+    gt = theta.grad.cpu().numpy().astype(np.float64)
+    for k in range(3):
+        ref = gt_ref[~fr, k]
+        err = np.abs(gt[~fr, k] - ref) / (np.abs(ref) + 1e-3 * np.abs(ref).max() + 1e-30)
+        assert float(np.median(err)) < 1e-5 and float((err > 1e-3).mean()) < 0.01, k
+    gsm = samples.grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(gsm - gsm_ref) / np.linalg.norm(gsm_ref) < 1e-3
