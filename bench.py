@@ -1,29 +1,42 @@
-"""Benchmark: semblance evaluations per second of the CMP scan on one MI355X.
+"""Benchmark: semblance evaluations per second of the parameter scan on one MI355X.
 
-Workload (one "step" = one cmp_scan call over the whole batch, i.e. the
-energy-coefficient pass plus the scan kernel): 20000 midpoints x fold 60 x
-2000 samples at dt = 2 ms (half-offsets U[0, 3000] m, 8 Ricker(30 Hz) events
-of random polarity per gather, SNR 2), 201 velocities 1400..5000 m/s, window
-15 samples.  Inputs are synthetic (the paper's datasets are not public) and
-resident in HBM before the timed region.
+The step (the timed unit, K of them): one cmp_scan call over the CMP-large
+workload -- 20000 midpoints x fold 60 x 2000 samples at dt = 2 ms
+(half-offsets U[0, 3000] m, 8 Ricker(30 Hz) events of random polarity per
+gather, SNR 2), 201 velocities 1400..5000 m/s, window 15.  A call is the
+window-energy pre-pass plus the scan kernel.  Inputs are synthetic (the
+paper's datasets are not public) and resident in HBM before the timed region.
+value = intersections (midpoints x samples x velocities x traces, every one
+counted) / wall-clock seconds per step.
 
-Prints one JSON line.  Fields beyond the driver's contract:
-  roofline      the scan kernel against the FP32 vector-ALU peak, with the
-                paper's per-intersection flop count 12 + 7w (Eq. 2) applied
-                to every intersection (12) and to every contributing window
-                (7w); time from HIP events around each scan call on the
-                stream it runs on;
-  cpu_baseline  the FP64 oracle on this host's cores over the first 128
-                gathers (same per-evaluation metric);
-  crs           the same metric for the 2D-CRS line (512 centrals, 270-trace
-                apertures, 21x21x41 parameters, w = 9), one timed call.
+Prints one JSON line.  Fields beyond the step itself:
+  roofline      the scan kernel against the FP32 vector-ALU peak.  Work per
+                launch = the paper's per-intersection flop count 12 + 7w
+                (Eq. 2), 12 on every intersection and 7w on every window that
+                lies on its trace (counted exactly in closed form); time =
+                HIP events recorded by the library around each scan-kernel
+                launch, on the stream it runs on, averaged over the K steps.
+                traffic = HBM bytes per launch from the rocprofv3 FETCH_SIZE /
+                WRITE_SIZE record in profiles/, or null when that record was
+                taken on other kernel sources than the ones built now;
+  crs           the 2D-CRS line: 512 centrals, +-4 gathers x fold 30 (270
+                traces), 1000 samples at 4 ms, A 21 x B 21 x v 41, window 9;
+  batched       4096 gathers of fold 8..120 and 500..2000 samples, 2867 CMP
+                jobs (101 velocities, w 11) and 1229 CRS jobs (11 x 11 x 21,
+                +-2 gathers, w 9), one persistent launch replayed from a
+                captured HIP graph;
+  refine        the CRS line again: a coarse 7 x 7 x 11 scan + 8 gradient-
+                ascent steps per output sample, captured in one HIP graph,
+                against the exhaustive 21 x 21 x 41 scan (time and semblance);
+  cpu_baseline  the FP64 oracle on this host's cores over the first gathers
+                of the CMP-large workload (same per-intersection metric).
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import platform
 import sys
 import time
 
@@ -33,29 +46,80 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 vector peak (published)
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "scan_kernel_cmp_large_traffic.txt")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cmp_valid_evals(h: np.ndarray, q: np.ndarray, ns: int, dt: float, w: int, ngathers: int) -> int:
+def eq2_flops(evals: int, valid: int, w: int) -> int:
+    """Eq. 2 work: 12 per intersection, 7w per window on its trace."""
+    return 12 * evals + 7 * w * valid
+
+
+def cmp_valid_evals(h: np.ndarray, q: np.ndarray, ns: int, dt: float, w: int) -> int:
     """Exact number of (gather, t0, q, trace) intersections whose window lies on
-    the trace, for uniform gathers.  tau(s) = sqrt(s^2 + q h^2/dt^2) grows with s,
-    so for each (trace, q) the contributing s form one interval:
-    hw <= floor(tau) <= ns - 2 - hw."""
+    the trace, for gathers of ns samples.  tau(s) = sqrt(s^2 + q h^2 / dt^2)
+    grows with s, so for each (trace, q) the contributing s form one interval:
+    hw <= tau < ns - 1 - hw."""
     hw = (w - 1) // 2
     gam = (h.astype(np.float64) ** 2 / (dt * dt))[:, None] * q.astype(np.float64)[None, :]
-    top = float(ns - 1 - hw)  # need tau < top
-    # largest s with s^2 + gam < top^2
+    top = float(ns - 1 - hw)
     lim = top * top - gam
     smax = np.where(lim > 0, np.ceil(np.sqrt(np.maximum(lim, 0))) - 1, -1.0)
     smax = np.minimum(smax, ns - 1)
-    # smallest s with tau >= hw: s^2 + gam >= hw^2
     low = hw * hw - gam
     smin = np.where(low > 0, np.ceil(np.sqrt(np.maximum(low, 0))), 0.0)
-    cnt = np.maximum(smax - smin + 1, 0)
-    return int(cnt.sum())
+    return int(np.maximum(smax - smin + 1, 0).sum())
+
+
+def _count_open(r1, r2, n):
+    """Integers s in [0, n-1] with r1 < s < r2 (elementwise; empty where r1 >= r2)."""
+    lo = np.maximum(np.floor(r1) + 1, 0)
+    hi = np.minimum(np.ceil(r2) - 1, n - 1)
+    return np.maximum(hi - lo + 1, 0)
+
+
+def crs_valid_fraction(gs, jobs, grid, w: int, js) -> float:
+    """Fraction of the intersections of jobs `js` whose window lies on the
+    trace.  With u(s) = T/dt^2 = s^2 + beta s + gamma (convex in s), a trace
+    contributes at s iff hw^2 <= u(s) < (ns_i - 1 - hw)^2, i.e. s lies in the
+    root interval of the upper bound minus that of the lower bound."""
+    hw = (w - 1) // 2
+    dt = gs.dt
+    A = grid.A.astype(np.float64)[:, None, None]
+    B = grid.B.astype(np.float64)[None, :, None]
+    q = grid.q.astype(np.float64)[None, None, :]
+    valid = total = 0.0
+    tp = gs.trace_ptr.astype(np.int64)
+    for j in js:
+        c = int(jobs.central[j])
+        n = int(gs.ns[c])
+        for g in jobs.apert_gather[jobs.apert_ptr[j]:jobs.apert_ptr[j + 1]]:
+            for i in range(tp[g], tp[g + 1]):
+                dm = float(gs.midpoint[i]) - float(gs.central_x[c])
+                h = float(gs.half_offset[i])
+                beta = (4 * A * dm + 2 * B * dm * dm) / dt
+                gamma = (4 * A * A * dm * dm + q * h * h) / (dt * dt)
+                beta, gamma = np.broadcast_arrays(beta, gamma)
+                top = float(gs.ns[g] - 1 - hw)
+
+                def roots(level):
+                    disc = beta * beta - 4 * (gamma - level)
+                    sq = np.sqrt(np.maximum(disc, 0))
+                    r1 = np.where(disc > 0, (-beta - sq) / 2, 0.0)
+                    r2 = np.where(disc > 0, (-beta + sq) / 2, 0.0)
+                    return r1, r2
+
+                u1, u2 = roots(top * top)
+                cnt = _count_open(u1, u2, n)
+                if hw > 0:
+                    l1, l2 = roots(float(hw * hw))
+                    cnt = cnt - _count_open(l1, l2, n)
+                valid += float(cnt.sum())
+                total += float(n) * cnt.size
+    return valid / total
 
 
 def main():
@@ -64,22 +128,37 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-crs", action="store_true", help="skip the CRS line measurement")
-    ap.add_argument("--gathers", type=int, default=20000, help="(testing only) fewer gathers")
+    ap.add_argument("--cmp-only", action="store_true", help="skip the CRS, batched and refinement legs")
+    ap.add_argument("--gathers", type=int, default=20000, help="(testing only) fewer CMP gathers")
+    ap.add_argument("--cpu-gathers", type=int, default=384, help="CMP gathers in the CPU oracle sample")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "this build has no multi-GPU path.", file=sys.stderr)
+              "there is no multi-GPU path to run.", file=sys.stderr)
         sys.exit(2)
 
     import torch
     import synth
     import paper_1907_11678_amd as semb
+    from paper_1907_11678_amd import profiling
 
     torch.cuda.set_device(0)
     dev = "cuda"
+    stream = torch.cuda.current_stream()
 
-    # ---- inputs -----------------------------------------------------------
+    if args.calibrate_copy > 0:
+        nb = args.calibrate_copy << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: 3 x {nb} bytes")
+        del src, dst
+
+    # ---- CMP large: the step ---------------------------------------------
     spec = synth.cmp_large_spec()
     spec.ngathers = args.gathers
     G, F, NS, W = spec.ngathers, spec.fold, spec.ns, 15
@@ -87,7 +166,7 @@ def main():
     host = torch.empty(G * F * NS, dtype=torch.float32).pin_memory()
     h = np.empty(G * F, np.float32)
     synth.cmp_fill(spec, host.numpy(), h)
-    log(f"generated {G} gathers in {time.time() - t:.1f} s")
+    log(f"generated {G} CMP gathers in {time.time() - t:.1f} s")
     gs = synth.uniform_cmp_layout(spec, host.numpy(), h)
     jobs = synth.cmp_jobs(gs)
     q_host = synth.cmp_large_grid()
@@ -103,10 +182,8 @@ def main():
     torch.cuda.synchronize()
 
     evals = G * NS * q_host.size * F
-    valid = cmp_valid_evals(h, q_host, NS, gs.dt, W, G) if G == spec.ngathers else None
-    flops = 12 * evals + 7 * W * valid
-
-    stream = torch.cuda.current_stream()
+    valid = cmp_valid_evals(h, q_host, NS, gs.dt, W)
+    flops = eq2_flops(evals, valid, W)
 
     def step():
         semb.cmp_scan(dg, dj, q, W, best, sb, st, ws, stream=stream)
@@ -114,23 +191,20 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for e0, e1 in ev:
-        e0.record(stream)
-        step()
-        e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    with semb.KernelTimer(args.steps) as kt:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
     value = evals / (wall / args.steps)
-    k_avg = sum(kms) / len(kms) * 1e-3
+    k_avg = sum(kt.ms) / len(kt.ms) * 1e-3
     achieved = flops / k_avg / 1e12
-    log(f"cmp_large: {ms_per_step:.1f} ms/step (events {[round(x, 1) for x in kms]}), "
-        f"{value:.3e} evals/s, valid fraction {valid / evals:.4f}")
+    traffic = profiling.current_traffic(TRAFFIC_RECORD)
+    log(f"cmp_large: {ms_per_step:.1f} ms/step, scan kernel {[round(x, 1) for x in kt.ms]} ms, "
+        f"{value:.3e} evals/s, valid fraction {valid / evals:.4f}, {achieved:.1f} TFLOP/s")
 
     out = {
         "metric": "semblance evals/s (trace-samples x params / s), CMP scan",
@@ -157,50 +231,33 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None,
-            "kernel": "scan_kernel (CMP, w=15), timed with the energy-coefficient pass it follows",
+            "traffic": traffic,
+            "kernel": "scan_kernel<CMP, w=15>",
             "flops_per_launch": flops,
             "avg_launch_ms": k_avg * 1e3,
+            "algorithmic_bytes_per_launch": 4 * (gs.samples.size + h.size + 3 * n),
         },
     }
+    del dg, ws, host
+    torch.cuda.empty_cache()
 
-    # ---- CRS line (context) -------------------------------------------------
-    if not args.no_crs:
-        del dg, ws
+    if not args.cmp_only:
+        out["crs"], fine = crs_leg(torch, synth, semb, dev, stream)
+        out["refine"] = refine_leg(torch, synth, semb, dev, stream, fine)
+        del fine
         torch.cuda.empty_cache()
-        wl = synth.crs_line()
-        cg, cj = wl.gathers, wl.jobs
-        dgc = semb.upload_gathers(cg.samples, cg.sample_off, cg.trace_ptr, cg.ns, cg.half_offset,
-                                  cg.midpoint, cg.central_x, cg.dt, device=dev)
-        djc = semb.upload_jobs(cj.central, cj.apert_ptr, cj.apert_gather, cj.out_off, cj.n_out, device=dev)
-        nc = cj.n_out
-        cb = torch.empty(nc, dtype=torch.int32, device=dev)
-        cs = torch.empty(nc, dtype=torch.float32, device=dev)
-        ct = torch.empty(nc, dtype=torch.float32, device=dev)
-        wsc = semb.alloc_workspace(dgc.nsamples)
-        A, B, qc = (torch.from_numpy(x).to(dev) for x in (wl.grid.A, wl.grid.B, wl.grid.q))
-        semb.crs_scan(dgc, djc, A, B, qc, wl.w, cb, cs, ct, wsc, stream=stream)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        semb.crs_scan(dgc, djc, A, B, qc, wl.w, cb, cs, ct, wsc, stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        cev = synth.count_evals(cg, cj, wl.grid)
-        out["crs"] = {"workload": "crs_line: 512 centrals, +-4 gathers x fold 30 (270 traces), "
-                                  "1000 samples (dt 4 ms), 21x21x41 parameters, window 9",
-                      "value": cev / (ms * 1e-3), "unit": "evals/s", "ms": ms,
-                      "tflops_nominal": cev * (12 + 7 * wl.w) / (ms * 1e-3) / 1e12}
-        log(f"crs_line: {ms:.1f} ms, {cev / (ms * 1e-3):.3e} evals/s")
+        out["batched"] = batched_leg(torch, synth, semb, dev, stream)
 
     # ---- CPU oracle baseline ---------------------------------------------
     if not args.no_cpu:
         import oracle
-        ng = min(128, G)
-        sub = synth.Gathers(gs.samples[:ng * F * NS], gs.sample_off[:ng], gs.trace_ptr[:ng + 1],
-                            gs.ns[:ng], gs.half_offset[:ng * F], gs.midpoint[:ng * F],
-                            gs.central_x[:ng], gs.dt)
+        ng = min(args.cpu_gathers, G)
+        cs = synth.cmp_large_spec()
+        cs.ngathers = ng
+        samples = np.empty(ng * F * NS, np.float32)
+        hh = np.empty(ng * F, np.float32)
+        synth.cmp_fill(cs, samples, hh)
+        sub = synth.uniform_cmp_layout(cs, samples, hh)
         sj = synth.cmp_jobs(sub)
         nt = oracle.max_threads()
         t = time.perf_counter()
@@ -208,11 +265,174 @@ def main():
         dtc = time.perf_counter() - t
         cev = ng * NS * q_host.size * F
         out["cpu_baseline"] = {"value": cev / dtc, "unit": "evals/s", "cores": nt, "kind": "oracle",
-                               "sample": f"first {ng} of the {G} gathers ({cev:.3e} evals, FP64, "
-                                         f"{dtc:.1f} s)"}
+                               "sample": f"first {ng} of the {G} CMP-large gathers ({cev:.3e} evals, "
+                                         f"FP64, {dtc:.1f} s)",
+                               "cpu": _cpu_model()}
         log(f"cpu oracle: {cev / dtc:.3e} evals/s on {nt} threads")
 
     print(json.dumps(out), flush=True)
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def _timed_replays(torch, g, stream, n):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        g.replay()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return [e0.elapsed_time(e1) for e0, e1 in ev]
+
+
+def crs_leg(torch, synth, semb, dev, stream):
+    wl = synth.crs_line()
+    cg, cj = wl.gathers, wl.jobs
+    dg = semb.upload_gathers(cg.samples, cg.sample_off, cg.trace_ptr, cg.ns, cg.half_offset, cg.midpoint,
+                             cg.central_x, cg.dt, device=dev)
+    dj = semb.upload_jobs(cj.central, cj.apert_ptr, cj.apert_gather, cj.out_off, cj.n_out, device=dev)
+    n = cj.n_out
+    best = torch.empty(n, dtype=torch.int32, device=dev)
+    sb = torch.empty(n, dtype=torch.float32, device=dev)
+    st = torch.empty(n, dtype=torch.float32, device=dev)
+    ws = semb.alloc_workspace(dg.nsamples)
+    A, B, q = (torch.from_numpy(x).to(dev) for x in (wl.grid.A, wl.grid.B, wl.grid.q))
+    semb.crs_scan(dg, dj, A, B, q, wl.w, best, sb, st, ws, stream=stream)
+    torch.cuda.synchronize()
+    with semb.KernelTimer(2) as kt:
+        t0 = time.perf_counter()
+        for _ in range(2):
+            semb.crs_scan(dg, dj, A, B, q, wl.w, best, sb, st, ws, stream=stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / 2
+    evals = synth.count_evals(cg, cj, wl.grid)
+    probe = np.linspace(0, cj.njobs - 1, 16).astype(int)
+    vf = crs_valid_fraction(cg, cj, wl.grid, wl.w, probe)
+    k_ms = sum(kt.ms) / len(kt.ms)
+    tflops = (12 * evals + 7 * wl.w * vf * evals) / (k_ms * 1e-3) / 1e12
+    log(f"crs_line: {wall * 1e3:.1f} ms/call, scan kernel {k_ms:.1f} ms, {evals / wall:.3e} evals/s, "
+        f"valid fraction ~{vf:.4f}, {tflops:.1f} TFLOP/s")
+    res = {"workload": "crs_line: 512 centrals, +-4 gathers x fold 30 (270 traces), 1000 samples (dt 4 ms), "
+                       "21x21x41 parameters, window 9",
+           "value": evals / wall, "unit": "evals/s", "ms_per_call": wall * 1e3, "evals": evals,
+           "kernel_ms": k_ms, "valid_fraction_16_centrals": vf,
+           "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tflops / PEAK_FP32_TFLOPS, "kernel": "scan_kernel<CRS, w=9>"}}
+    fine = {"wl": wl, "dg": dg, "dj": dj, "s_best": sb.cpu().numpy().astype(np.float64), "ms": wall * 1e3}
+    return res, fine
+
+
+def refine_leg(torch, synth, semb, dev, stream, fine):
+    wl, dg, dj = fine["wl"], fine["dg"], fine["dj"]
+    n = wl.jobs.n_out
+    coarse = synth.crs_coarse_grid()
+    A, B, q = (torch.from_numpy(x).to(dev) for x in (coarse.A, coarse.B, coarse.q))
+    best = torch.empty(n, dtype=torch.int32, device=dev)
+    s0 = torch.empty(n, device=dev)
+    st0 = torch.empty(n, device=dev)
+    theta = torch.empty((n, 3), device=dev)
+    S = torch.empty(n, device=dev)
+    st = torch.empty(n, device=dev)
+    ws = semb.alloc_workspace(dg.nsamples)
+
+    def cell(v):
+        v = np.asarray(v, np.float64)
+        return float((v.max() - v.min()) / max(v.size - 1, 1))
+
+    scale = (cell(coarse.A), cell(coarse.B), cell(coarse.q))
+    lo = (float(coarse.A.min()), float(coarse.B.min()), float(coarse.q.min()))
+    hi = (float(coarse.A.max()), float(coarse.B.max()), float(coarse.q.max()))
+
+    s = torch.cuda.Stream()
+
+    def run():
+        semb.crs_scan(dg, dj, A, B, q, wl.w, best, s0, st0, ws, stream=s)
+        semb.theta_from_best(best, q, theta, A=A, B=B, stream=s)
+        semb.refine(dg, dj, 1, theta, wl.w, S, st, steps=8, eta0=0.5, scale=scale, lo=lo, hi=hi, stream=s)
+
+    s.wait_stream(stream)
+    with torch.cuda.stream(s):
+        run()
+    stream.wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        run()
+    g.replay()
+    torch.cuda.synchronize()
+    ms = _timed_replays(torch, g, torch.cuda.current_stream(), 3)
+    t_ms = sorted(ms)[1]
+    Sr = S.cpu().numpy().astype(np.float64)
+    Sf = fine["s_best"]
+    sel = Sf > 0.1
+    d = (Sr - Sf)[sel]
+    res = {"workload": "crs_line data, coarse 7x7x11 scan + 8 ascent steps per output sample, one HIP graph",
+           "ms": t_ms, "exhaustive_ms": fine["ms"], "speedup_vs_exhaustive": fine["ms"] / t_ms,
+           "rows_compared": int(sel.sum()),
+           "s_gap_median": float(np.median(d)), "s_gap_p5": float(np.percentile(d, 5)),
+           "frac_at_least_fine": float((d >= -1e-4).mean()),
+           "mean_s_coarse": float(s0.cpu().numpy().mean()), "mean_s_refined": float(Sr.mean()),
+           "mean_s_fine": float(Sf.mean())}
+    log(f"refine: {t_ms:.1f} ms vs exhaustive {fine['ms']:.1f} ms; S gap median {res['s_gap_median']:+.4f}, "
+        f"p5 {res['s_gap_p5']:+.4f}, >= fine-1e-4 on {res['frac_at_least_fine']:.3f} of {int(sel.sum())} rows")
+    return res
+
+
+def batched_leg(torch, synth, semb, dev, stream):
+    t = time.time()
+    bw = synth.batched_line()
+    log(f"generated the batched line in {time.time() - t:.1f} s")
+    gs, jobs = bw.gathers, bw.jobs
+    dg = semb.upload_gathers(gs.samples, gs.sample_off, gs.trace_ptr, gs.ns, gs.half_offset, gs.midpoint,
+                             gs.central_x, gs.dt, device=dev)
+    dj = semb.upload_jobs(jobs.central, jobs.apert_ptr, jobs.apert_gather, jobs.out_off, jobs.n_out, device=dev)
+    kind = torch.from_numpy(bw.kind).to(dev)
+    tiles, ng, npart = semb.batch_plan(bw.kind, jobs.central, jobs.apert_ptr, jobs.apert_gather, gs.ns,
+                                       gs.trace_ptr, bw.grid_cmp.n, bw.grid_crs.n, 256)
+    dtiles = torch.from_numpy(tiles).to(dev)
+    ws = semb.alloc_batch_workspace(dg.nsamples, bw.w_cmp, bw.w_crs, ng, npart)
+    qc = torch.from_numpy(bw.grid_cmp.q).to(dev)
+    A, B, qr = (torch.from_numpy(x).to(dev) for x in (bw.grid_crs.A, bw.grid_crs.B, bw.grid_crs.q))
+    n = jobs.n_out
+    best = torch.empty(n, dtype=torch.int32, device=dev)
+    sb = torch.empty(n, dtype=torch.float32, device=dev)
+    st = torch.empty(n, dtype=torch.float32, device=dev)
+    s = torch.cuda.Stream()
+
+    def run():
+        semb.scan_batch(dg, dj, kind, qc, bw.w_cmp, A, B, qr, bw.w_crs, dtiles, ng, npart, best, sb, st, ws,
+                        stream=s)
+
+    s.wait_stream(stream)
+    with semb.KernelTimer(1) as kt:
+        with torch.cuda.stream(s):
+            run()
+        torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        run()
+    g.replay()
+    torch.cuda.synchronize()
+    ms = _timed_replays(torch, g, torch.cuda.current_stream(), 3)
+    t_ms = sorted(ms)[1]
+    ev_c = synth.count_evals(gs, bw.subset(0), bw.grid_cmp)
+    ev_r = synth.count_evals(gs, bw.subset(1), bw.grid_crs)
+    ev = ev_c + ev_r
+    log(f"batched: graph {t_ms:.1f} ms (kernel {kt.ms[0]:.1f} ms eager), {ev / (t_ms * 1e-3):.3e} evals/s, "
+        f"{tiles.shape[0]} tiles")
+    return {"workload": "batched_line: 4096 gathers, fold 8-120, 500-2000 samples (dt 4 ms); 2867 CMP jobs "
+                        "(101 velocities, w 11) + 1229 CRS jobs (11x11x21, +-2 gathers, w 9); one persistent "
+                        "launch in a HIP graph",
+            "value": ev / (t_ms * 1e-3), "unit": "evals/s", "graph_ms": t_ms, "kernel_ms_eager": kt.ms[0],
+            "evals": ev, "evals_cmp": ev_c, "evals_crs": ev_r, "tiles": int(tiles.shape[0])}
 
 
 if __name__ == "__main__":

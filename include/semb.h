@@ -266,6 +266,19 @@ semb_status scan_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_
                        const semb_tile *tiles, int64_t ntiles, int32_t ngroups, int32_t nparts,
                        const semb_outputs *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Kernel timing for measurement.  After semb_kernel_timer_start(capacity),
+ * the next `capacity` launches of a call's main kernel made by this thread
+ * (the scan kernel of cmp_scan / crs_scan, the persistent kernel of
+ * scan_batch, the kernels of stack, semblance_grad and semb_refine; not the
+ * window-energy pre-pass) are bracketed by a pair of HIP events recorded on
+ * the call's stream.  Launches on a stream that is being captured into a
+ * graph are not timed.  semb_kernel_timer_stop waits for the recorded
+ * events, writes the number of timed launches to *count and the first
+ * min(count, ms_len) durations in milliseconds to ms, then releases the
+ * events.  The events belong to the device current at start.  [host] */
+semb_status semb_kernel_timer_start(int32_t capacity);
+semb_status semb_kernel_timer_stop(int32_t *count, float *ms, int32_t ms_len);
+
 /* Message describing the last non-OK status returned on this thread. [host] */
 const char *semb_last_error(void);
 

@@ -106,6 +106,10 @@ def lib():
         L.semb_refine.restype = C.c_int
         L.semb_theta_from_best.argtypes = [P, i64, P, i32, P, i32, P, i32, P, P]
         L.semb_theta_from_best.restype = C.c_int
+        L.semb_kernel_timer_start.argtypes = [i32]
+        L.semb_kernel_timer_start.restype = C.c_int
+        L.semb_kernel_timer_stop.argtypes = [P, P, i32]
+        L.semb_kernel_timer_stop.restype = C.c_int
         L.semb_last_error.restype = C.c_char_p
         L.semb_version.restype = C.c_char_p
         _lib = L
@@ -122,6 +126,27 @@ def version() -> str:
 
 def workspace_bytes(nsamples: int) -> int:
     return int(lib().semb_workspace_bytes(int(nsamples)))
+
+
+class KernelTimer:
+    """Context manager around semb_kernel_timer_start / _stop: collects the
+    durations (ms) of the main-kernel launches this thread makes inside the
+    block, in launch order, into `.ms` on exit."""
+
+    def __init__(self, capacity: int = 256):
+        self.capacity = int(capacity)
+        self.ms: list[float] = []
+
+    def __enter__(self):
+        _check(lib().semb_kernel_timer_start(self.capacity))
+        return self
+
+    def __exit__(self, *exc):
+        n = C.c_int32(0)
+        buf = (C.c_float * self.capacity)()
+        _check(lib().semb_kernel_timer_stop(C.byref(n), buf, self.capacity))
+        self.ms = [float(buf[i]) for i in range(min(n.value, self.capacity))]
+        return False
 
 
 def _check(status: int):

@@ -35,6 +35,51 @@ semb_status hip_status(hipError_t e, const char *what)
     return fail(SEMB_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Per-thread kernel timer: event pairs recorded around main-kernel launches.
+struct KernelTimer {
+    std::vector<hipEvent_t> start, stop;
+    int used = 0;
+    bool on = false;
+
+    void release()
+    {
+        for (hipEvent_t e : start)
+            if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : stop)
+            if (e) (void)hipEventDestroy(e);
+        start.clear();
+        stop.clear();
+        used = 0;
+        on = false;
+    }
+};
+
+thread_local KernelTimer g_timer;
+
+// Run `launch` (which enqueues one kernel on `stream`); bracket it with this
+// thread's next event pair when the timer is on and the stream is not being
+// captured.
+template <class F>
+hipError_t timed(hipStream_t stream, F launch)
+{
+    KernelTimer &t = g_timer;
+    bool rec = false;
+    if (t.on && t.used < (int)t.start.size()) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        rec = hipStreamIsCapturing(stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
+    }
+    if (rec) {
+        const hipError_t e = hipEventRecord(t.start[t.used], stream);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = launch();
+    if (rec && e == hipSuccess) {
+        e = hipEventRecord(t.stop[t.used], stream);
+        if (e == hipSuccess) ++t.used;
+    }
+    return e;
+}
+
 constexpr size_t kAlign = 256;
 constexpr int kScanCap = 2048;  // LDS positions per stage in the scan kernel (>= ns_max)
 
@@ -158,7 +203,8 @@ semb_status scan_common(int kind, const semb_gathers *g, const semb_jobs *jobs, 
     a.s_best = out->s_best;
     a.stack = out->stack;
     a.panel = out->panel;
-    return hip_status(semb::launch_scan(kind, a, stream), crs ? "crs_scan launch" : "cmp_scan launch");
+    return hip_status(timed(stream, [&] { return semb::launch_scan(kind, a, stream); }),
+                      crs ? "crs_scan launch" : "cmp_scan launch");
 }
 
 semb_status point_common(bool grad, const semb_gathers *g, const semb_jobs *jobs, int32_t kind,
@@ -197,8 +243,8 @@ semb_status point_common(bool grad, const semb_gathers *g, const semb_jobs *jobs
     a.g_theta = g_theta;
     a.g_samples = g_samples;
     a.w = w;
-    if (grad) return hip_status(semb::launch_grad(kind, a, stream), "semblance_grad launch");
-    return hip_status(semb::launch_point(kind, a, stream), "stack launch");
+    if (grad) return hip_status(timed(stream, [&] { return semb::launch_grad(kind, a, stream); }), "semblance_grad launch");
+    return hip_status(timed(stream, [&] { return semb::launch_point(kind, a, stream); }), "stack launch");
 }
 
 constexpr int kBatchBlock = 16;  // parameters per block of the batch kernel (8 waves x 2)
@@ -378,7 +424,7 @@ semb_status scan_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_
     a.best = out->best;
     a.s_best = out->s_best;
     a.stack = out->stack;
-    return hip_status(semb::launch_batch(a, ngroups, stream), "scan_batch launch");
+    return hip_status(timed(stream, [&] { return semb::launch_batch(a, ngroups, stream); }), "scan_batch launch");
 }
 
 
@@ -457,7 +503,7 @@ semb_status semb_refine(const semb_gathers *g, const semb_jobs *jobs, int32_t ki
         r.lo[k] = o->lo[k];
         r.hi[k] = o->hi[k];
     }
-    return hip_status(semb::launch_refine(kind, a, r, stream), "semb_refine launch");
+    return hip_status(timed(stream, [&] { return semb::launch_refine(kind, a, r, stream); }), "semb_refine launch");
 }
 
 semb_status semb_theta_from_best(const int32_t *best, int64_t n_out, const float *A, int32_t nA, const float *B,
@@ -469,6 +515,44 @@ semb_status semb_theta_from_best(const int32_t *best, int64_t n_out, const float
     if ((A && nA < 1) || (B && nB < 1)) return fail(SEMB_EINVAL, "nA and nB must be >= 1");
     return hip_status(semb::launch_theta_from_best(best, n_out, A, A ? nA : 1, B, B ? nB : 1, q, nq, theta, stream),
                       "semb_theta_from_best launch");
+}
+
+semb_status semb_kernel_timer_start(int32_t capacity)
+{
+    if (capacity < 1 || capacity > 65536) return fail(SEMB_EINVAL, "timer capacity must be in 1..65536");
+    KernelTimer &t = g_timer;
+    t.release();
+    t.start.assign(capacity, nullptr);
+    t.stop.assign(capacity, nullptr);
+    for (int32_t i = 0; i < capacity; ++i) {
+        hipError_t e = hipEventCreate(&t.start[i]);
+        if (e == hipSuccess) e = hipEventCreate(&t.stop[i]);
+        if (e != hipSuccess) {
+            t.release();
+            return hip_status(e, "semb_kernel_timer_start: hipEventCreate");
+        }
+    }
+    t.on = true;
+    return SEMB_OK;
+}
+
+semb_status semb_kernel_timer_stop(int32_t *count, float *ms, int32_t ms_len)
+{
+    KernelTimer &t = g_timer;
+    t.on = false;
+    const int n = t.used;
+    if (count) *count = n;
+    semb_status st = SEMB_OK;
+    for (int i = 0; i < n && i < ms_len && ms; ++i) {
+        hipError_t e = hipEventSynchronize(t.stop[i]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], t.start[i], t.stop[i]);
+        if (e != hipSuccess) {
+            st = hip_status(e, "semb_kernel_timer_stop");
+            break;
+        }
+    }
+    t.release();
+    return st;
 }
 
 const char *semb_last_error(void) { return g_last_error.c_str(); }

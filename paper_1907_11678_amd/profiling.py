@@ -1,0 +1,142 @@
+"""Measurement helpers: summaries of rocprofv3 output and the HBM-traffic
+record of a kernel.
+
+    python -m paper_1907_11678_amd.profiling stats <kernel_stats.csv>
+        Markdown table of a `rocprofv3 --kernel-trace --stats
+        --output-format csv` run (per kernel: calls, total, average, share).
+
+    python -m paper_1907_11678_amd.profiling traffic <fetch_csv> <write_csv>
+            <kernel-substring> <copy-bytes> <out.txt>
+        Reduce two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs
+        (counter_collection.csv) to bytes per launch of the kernel whose name
+        contains <kernel-substring>.  The same runs must contain a plain
+        device-to-device copy of <copy-bytes> bytes (bench.py
+        --calibrate-copy); the copy's own FETCH_SIZE and WRITE_SIZE give the
+        factor that turns the counters into bytes.  The record carries the
+        digest of the kernel sources, so a reader can tell whether it still
+        describes the code that is built.
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import os
+import sys
+from collections import defaultdict
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+# sources whose change invalidates a traffic record of the scan kernels
+KERNEL_SOURCES = ("csrc/scan.hip", "csrc/internal.h", "csrc/traveltime.h", "build.py")
+COPY_KERNEL = "copyBuffer"
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(PKG, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_stats_table(path: str, top: int = 12) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = ["| kernel | calls | total ms | average ms | min ms | max ms | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        ns = float(r["TotalDurationNs"])
+        out.append(f"| `{r['Name']}` | {r['Calls']} | {ns / 1e6:.3f} | {float(r['AverageNs']) / 1e6:.3f} | "
+                   f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def _per_dispatch(path: str, counter: str):
+    """{kernel name: [value per dispatch]} for one counter (summed over the
+    dimensions rocprofv3 may report separately)."""
+    acc = defaultdict(float)
+    names = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        d = int(r["Dispatch_Id"])
+        acc[d] += float(r["Counter_Value"])
+        names[d] = r["Kernel_Name"]
+    by = defaultdict(list)
+    for d in sorted(acc):
+        by[names[d]].append(acc[d])
+    return by
+
+
+def _mean_of(by, sub: str, largest: bool = False):
+    """Mean counter value over the dispatches of the kernel matching `sub`;
+    with largest=True only over the dispatches within 2x of the largest (the
+    calibration copies, not the small uploads that use the same kernel)."""
+    vals = [v for k, vs in by.items() if sub in k for v in vs]
+    if not vals:
+        raise SystemExit(f"no dispatch of a kernel matching {sub!r}")
+    if largest:
+        top = max(vals)
+        vals = [v for v in vals if v >= 0.5 * top]
+    return sum(vals) / len(vals), len(vals), [k for k in by if sub in k][0]
+
+
+def traffic_record(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int) -> dict:
+    fb = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    wb = _per_dispatch(write_csv, "WRITE_SIZE")
+    cf, ncf, _ = _mean_of(fb, COPY_KERNEL, largest=True)
+    cw, ncw, _ = _mean_of(wb, COPY_KERNEL, largest=True)
+    kf, nkf, name = _mean_of(fb, kernel)
+    kw, nkw, _ = _mean_of(wb, kernel)
+    f_fetch = copy_bytes / cf  # bytes per counter unit, from the copy's reads
+    f_write = copy_bytes / cw
+    return {
+        "kernel": name, "source_digest": source_digest(),
+        "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+        "fetch_factor": f_fetch, "write_factor": f_write,
+        "fetch_kib_per_launch": kf, "write_kib_per_launch": kw, "launches": min(nkf, nkw),
+        "fetch_bytes_per_launch": kf * f_fetch, "write_bytes_per_launch": kw * f_write,
+        "traffic_bytes_per_launch": kf * f_fetch + kw * f_write,
+    }
+
+
+def write_record(rec: dict, path: str, header: str = ""):
+    with open(path, "w") as f:
+        if header:
+            f.write(header.rstrip() + "\n\n")
+        for k, v in rec.items():
+            f.write(f"{k}: {v}\n")
+
+
+def read_record(path: str) -> dict | None:
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ": " in line and not line.startswith(("#", " ", "|", "`")):
+            k, v = line.rstrip("\n").split(": ", 1)
+            rec[k.strip()] = v.strip()
+    return rec if "traffic_bytes_per_launch" in rec else None
+
+
+def current_traffic(path: str) -> float | None:
+    """Bytes per launch from a traffic record, or None when the record is
+    missing or was taken on kernel sources other than the ones built now."""
+    rec = read_record(path)
+    if rec is None or rec.get("source_digest") != source_digest():
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
+def main(argv):
+    if len(argv) >= 2 and argv[0] == "stats":
+        print(kernel_stats_table(argv[1]))
+    elif len(argv) == 6 and argv[0] == "traffic":
+        rec = traffic_record(argv[1], argv[2], argv[3], int(argv[4]))
+        write_record(rec, argv[5])
+        print("\n".join(f"{k}: {v}" for k, v in rec.items()))
+    else:
+        print(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))

@@ -1,0 +1,49 @@
+"""Host-side counts that bench.py's roofline figures rest on: the number of
+intersections whose window lies on the trace, from closed forms, against a
+direct evaluation of the validity rule on every (t0, parameter, trace)."""
+from __future__ import annotations
+
+import numpy as np
+
+import bench
+import synth
+
+
+def _brute_valid(gs, jobs, grid, w):
+    hw = (w - 1) // 2
+    tp = gs.trace_ptr.astype(np.int64)
+    A = grid.A.astype(np.float64)[:, None, None, None]
+    B = grid.B.astype(np.float64)[None, :, None, None]
+    q = grid.q.astype(np.float64)[None, None, :, None]
+    valid = total = 0
+    for j in range(jobs.njobs):
+        c = int(jobs.central[j])
+        s = np.arange(int(gs.ns[c]))[None, None, None, :] * gs.dt
+        for g in jobs.apert_gather[jobs.apert_ptr[j]:jobs.apert_ptr[j + 1]]:
+            for i in range(tp[g], tp[g + 1]):
+                dm = float(gs.midpoint[i]) - float(gs.central_x[c])
+                h = float(gs.half_offset[i])
+                T = (s + 2 * A * dm) ** 2 + 2 * s * B * dm * dm + q * h * h
+                k = np.floor(np.sqrt(np.maximum(T, 0)) / gs.dt)
+                ok = (T >= 0) & (k >= hw) & (k + hw + 1 <= int(gs.ns[g]) - 1)
+                valid += int(ok.sum())
+                total += ok.size
+    return valid, total
+
+
+def test_cmp_valid_count_is_exact():
+    wl = synth.cmp_plain(ids=[0, 1, 2])
+    gs = wl.gathers
+    v, _ = _brute_valid(gs, wl.jobs, wl.grid, wl.w)
+    assert bench.cmp_valid_evals(gs.half_offset, wl.grid.q, int(gs.ns[0]), gs.dt, wl.w) == v
+
+
+def test_crs_valid_fraction_is_exact():
+    wl = synth.crs_line(centrals=[20, 300], grid=synth.crs_coarse_grid())
+    v, t = _brute_valid(wl.gathers, wl.jobs, wl.grid, wl.w)
+    f = bench.crs_valid_fraction(wl.gathers, wl.jobs, wl.grid, wl.w, range(wl.jobs.njobs))
+    assert abs(f - v / t) < 1e-15
+
+
+def test_eq2_flops():
+    assert bench.eq2_flops(10, 7, 9) == 120 + 7 * 9 * 7
