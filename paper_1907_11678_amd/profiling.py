@@ -25,13 +25,16 @@ import sys
 from collections import defaultdict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-# sources whose change invalidates a traffic record of the scan kernels
-KERNEL_SOURCES = ("csrc/scan.hip", "csrc/internal.h", "csrc/traveltime.h", "build.py")
+# sources whose change (with the compiler flags) invalidates a traffic record
+# of the scan kernels
+KERNEL_SOURCES = ("csrc/scan.hip", "csrc/internal.h", "csrc/traveltime.h")
 COPY_KERNEL = "copyBuffer"
 
 
 def source_digest() -> str:
+    from paper_1907_11678_amd.build import FLAGS
     h = hashlib.sha256()
+    h.update(" ".join(f for f in FLAGS if not f.startswith("-I")).encode())
     for rel in KERNEL_SOURCES:
         with open(os.path.join(PKG, rel), "rb") as f:
             h.update(rel.encode() + b"\0" + f.read())

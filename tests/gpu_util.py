@@ -12,7 +12,7 @@ import numpy as np
 FRAGILE_TAU = 1e-8
 FRAGILE_T_REL = 1e-13
 
-# Tolerances ("parity"):
+# Tolerances:
 S_TOL = 1e-5           # |S_gpu - S_oracle| on rows whose contributing set is not fragile
 PICK_GAP = 1e-4        # picks must be identical where best and runner-up differ by more
 STACK_TOL = 2e-5       # |stack_gpu - stack_oracle| relative to the row's sample scale
