@@ -142,37 +142,78 @@ window_energy_kernel(const float *__restrict__ samples, const int64_t *__restric
 // One tile of the scan: output samples 64*sblk .. 64*sblk+63 of a job and
 // flat parameter indices [pbeg, pend).  KIND: SEMB_KIND_CMP / SEMB_KIND_CRS.
 // W: window.  P: parameters per lane.  NW: waves per workgroup.  CAP: LDS
-// sample positions per stage.  BRANCHY: windows behind a per-parameter branch
-// (skips off-trace windows) instead of the branch-free form (keeps every
-// window's loads in flight).
+// sample positions per stage.  TMAX: traces whose metadata is held in LDS at
+// once.  BRANCHY: windows behind a per-parameter branch (skips off-trace
+// windows) instead of the branch-free form (keeps every window's loads in
+// flight).
+//
+// Per parameter block the tile makes three kinds of pass:
+//   * the trace pass (all threads, one trace each): the sample range every
+//     trace can be touched in by the block, bounded by interval arithmetic
+//     over the block's parameter box (the paper's min/max of the k1 indices);
+//   * per chunk, the stage: every wave packs the next traces whose ranges fit
+//     in CAP (the same prefix scan in every wave, so no wave waits for
+//     another to decide), then the waves move the ranges into LDS with direct
+//     global->LDS loads;
+//   * the hot loop over the staged traces.
+// The traces' metadata (first sample, length, h^2/dt^2, dm) is loaded into
+// LDS once per tile when the aperture has at most TMAX traces, else once per
+// TMAX-trace part of it.
 // ---------------------------------------------------------------------------
-template <int KIND, int W, int P, int NW, int CAP>
+template <int KIND, int W, int P, int NW, int CAP, int TMAX>
 struct StageLds {
     float lf[CAP];                                  // staged samples
     float lu0[CAP], lu1[CAP], lu2[CAP];             // their window energy (Gram form)
     double2 tab[KIND == SEMB_KIND_CRS ? NW * P : 1][WAVE];  // CRS: (2 alpha + beta, alpha^2 + gamma)
-    double t_cc[WAVE];                              // h^2/dt^2 per staged trace
-    int2 tinfo[WAVE];                               // (base - lo, ns - 1 - W)
-    long long t_src[WAVE];                          // element of the first staged sample
-    int t_len[WAVE], t_base[WAVE];
-    float t_dm[WAVE];
+    // the traces of the current part: fixed per tile ...
+    long long t_base[TMAX];                         // element of the trace's sample 0
+    double t_cc[TMAX];                              // h^2/dt^2
+    int t_ns[TMAX];
+    float t_dm[TMAX];                               // midpoint displacement (CRS)
+    // ... and per parameter block
+    int t_lo[TMAX], t_len[TMAX];                    // staged range [lo, lo + len)
+    int t_lim[TMAX];                                // last valid window start, -1: nothing staged
+    int t_off[TMAX];                                // LDS position of sample 0 in its chunk
     double pq[NW * P], pA[NW * P], pB[NW * P];      // the current parameter block
+    double box[6];                                  // its bounds: q, A, B (lo, hi)
     int ag_s[SEMB_APERT_LIMIT];
     int ag_cum[SEMB_APERT_LIMIT + 1];
-    int nfit;
 };
+
+// Metadata of traces [tA, tA + nt) of the aperture into L.t_* (all threads).
+template <int KIND, class LDS>
+__device__ __forceinline__ void load_traces(const GatherView &g, LDS &L, int na, int tA, int nt, double xc,
+                                            double inv_dt, int nthreads)
+{
+    for (int e = threadIdx.x; e < nt; e += nthreads) {
+        const int t = tA + e;
+        int k = 0;
+        while (k + 1 < na && L.ag_cum[k + 1] <= t) ++k;
+        const int gg = L.ag_s[k];
+        const int li = t - L.ag_cum[k];
+        const int i = g.trace_ptr[gg] + li;
+        const int nsg = g.ns[gg];
+        L.t_base[e] = g.sample_off[gg] + (long long)li * nsg;
+        L.t_ns[e] = nsg;
+        const double h = g.half_offset[i];
+        L.t_cc[e] = h * h * inv_dt * inv_dt;
+        // the displacement as the kernels use it: rounded to FP32
+        L.t_dm[e] = KIND == SEMB_KIND_CRS ? (float)((double)g.midpoint[i] - xc) : 0.f;
+    }
+}
 
 // All threads of the workgroup call this together.  On return, lane l of
 // wave 0 holds the pick of output sample 64*sblk + l over [pbeg, pend):
 // bS (negative if the lane's sample lies beyond the job's trace length), bI,
 // bSt.  panel: optional [row][npar] semblance of every cell.
-template <int KIND, int W, int P, int NW, int CAP, bool BRANCHY>
+template <int KIND, int W, int P, int NW, int CAP, int TMAX, bool BRANCHY>
 __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv, const ParamView &pv,
-                                          StageLds<KIND, W, P, NW, CAP> &L, int job, int sblk, int pbeg,
+                                          StageLds<KIND, W, P, NW, CAP, TMAX> &L, int job, int sblk, int pbeg,
                                           int pend, float *panel, float &bS, int &bI, float &bSt)
 {
     constexpr int HW = (W - 1) / 2;
     constexpr int NT = NW * P;  // parameters per block
+    constexpr int NTH = NW * WAVE;
     constexpr bool CRS = KIND == SEMB_KIND_CRS;
 
     const int tid = threadIdx.x;
@@ -213,15 +254,18 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
     const int ntr = L.ag_cum[na];
     const double xc = CRS ? (double)g.central_x[c] : 0.0;
     const double inv_dt = 1.0 / (double)g.dt;
+    const bool resident = ntr <= TMAX;  // one part: metadata loaded once per tile
+    if (resident) load_traces<KIND>(g, L, na, 0, ntr, xc, inv_dt, NTH);
 
     const double sd = (double)s;
-    const double s2 = sd * sd;
+    // s^2, but 1e-300 at s = 0, so that T = 0 from a zero offset and zero
+    // displacement stays positive (tau ~ 1e-150: window start -hw, fraction 0)
+    const double s2e = s > 0 ? sd * sd : 1e-300;
 
     for (int pb = pbeg; pb < pend; pb += NT) {
         // ---- this block's parameters, decoded once by wave 0 (one per lane) into
         // LDS, with their bounds reduced across the wave.  The previous block
         // ended with a barrier, so the parameter arrays are free.
-        double qlo = 0.0, qhi = 0.0, Alo = 0.0, Ahi = 0.0, Blo = 0.0, Bhi = 0.0;
         if (wv == 0) {
             const int th = pb + lane;
             const bool on = lane < NT && th < pend;
@@ -240,13 +284,21 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                 L.pA[lane] = Av;
                 L.pB[lane] = Bv;
             }
-            qlo = wave_min(on ? qv : 1e300);
-            qhi = wave_max(on ? qv : -1e300);
+            const double qlo = wave_min(on ? qv : 1e300), qhi = wave_max(on ? qv : -1e300);
+            double Alo = 0.0, Ahi = 0.0, Blo = 0.0, Bhi = 0.0;
             if (CRS) {
                 Alo = wave_min(on ? Av : 1e300);
                 Ahi = wave_max(on ? Av : -1e300);
                 Blo = wave_min(on ? Bv : 1e300);
                 Bhi = wave_max(on ? Bv : -1e300);
+            }
+            if (lane == 0) {
+                L.box[0] = qlo;
+                L.box[1] = qhi;
+                L.box[2] = Alo;
+                L.box[3] = Ahi;
+                L.box[4] = Blo;
+                L.box[5] = Bhi;
             }
         }
 
@@ -259,32 +311,25 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
             Mc[p] = 0.f;
         }
 
-        for (int t0 = 0; t0 < ntr;) {
-            // ---- wave 0: sample range of the next traces, packed into LDS ----
-            if (wv == 0) {
-                const int t = t0 + lane;
-                int len = 0, lo = 0, nsg = 0;
-                long long src = 0;
-                double cc = 0.0, dm = 0.0;
-                if (t < ntr) {
-                    int k = 0;
-                    while (k + 1 < na && L.ag_cum[k + 1] <= t) ++k;
-                    const int gg = L.ag_s[k];
-                    const int li = t - L.ag_cum[k];
-                    const int i = g.trace_ptr[gg] + li;
-                    nsg = g.ns[gg];
-                    src = g.sample_off[gg] + (long long)li * nsg;
-                    const double h = g.half_offset[i];
-                    cc = h * h * inv_dt * inv_dt;
-                    // the displacement as the kernels use it: rounded to FP32
-                    dm = CRS ? (double)(float)((double)g.midpoint[i] - xc) : 0.0;
-                    // bounds of tau^2 over the tile (interval arithmetic, FP64)
+        for (int tA = 0; tA < ntr; tA += TMAX) {
+            const int nt = min(TMAX, ntr - tA);
+            __syncthreads();  // parameters and box visible; the previous part is done with L.t_*
+            if (!resident) load_traces<KIND>(g, L, na, tA, nt, xc, inv_dt, NTH);
+            // ---- trace pass: the range of samples the block can touch --------
+            {
+                const double qlo = L.box[0], qhi = L.box[1];
+                for (int e = tid; e < nt; e += NTH) {
+                    const double cc = L.t_cc[e];
+                    const int nsg = L.t_ns[e];
+                    int len = 0, lo = 0;
                     double Tlo, Thi;
                     const double gl = fmin(qlo * cc, qhi * cc), gh = fmax(qlo * cc, qhi * cc);
                     if (!CRS) {
                         Tlo = (double)s0 * s0 + gl;
                         Thi = (double)s1 * s1 + gh;
                     } else {
+                        const double Alo = L.box[2], Ahi = L.box[3], Blo = L.box[4], Bhi = L.box[5];
+                        const double dm = L.t_dm[e];
                         const double ai = 2.0 * dm * inv_dt, bi = 2.0 * dm * dm * inv_dt;
                         const double al = fmin(Alo * ai, Ahi * ai), ah = fmax(Alo * ai, Ahi * ai);
                         const double bl = Blo * bi, bh = Bhi * bi;  // bi >= 0
@@ -307,119 +352,155 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                             len = (int)(l1 - l0 + 1);
                         }
                     }
+                    L.t_lo[e] = lo;
+                    L.t_len[e] = len;
+                    // a trace without staged samples gets lim = -1: none of its windows count
+                    L.t_lim[e] = len > 0 ? nsg - 1 - W : -1;
                 }
+            }
+            __syncthreads();
+
+            for (int cb = 0; cb < nt;) {
+                // ---- pack the next traces into one stage (every wave alike) -----
+                const int e = cb + lane;
+                int len = e < nt ? L.t_len[e] : 0;
                 int incl = len;
 #pragma unroll
                 for (int o = 1; o < WAVE; o <<= 1) {
                     const int v = __shfl_up(incl, o, WAVE);
                     if (lane >= o) incl += v;
                 }
-                const bool fits = (t < ntr) && incl <= CAP;
+                const bool fits = e < nt && incl <= CAP;
                 const unsigned long long nf = __ballot(!fits);
                 int nfit = nf ? (__ffsll((long long)nf) - 1) : WAVE;
-                nfit = min(nfit, ntr - t0);
-                if (nfit == 0) {  // a single range larger than CAP: the host keeps ns_max <= CAP
+                nfit = min(nfit, nt - cb);
+                if (nfit == 0) {  // a range larger than CAP: excluded by the host (ns_max <= CAP)
                     nfit = 1;
-                    if (lane == 0) len = min(len, CAP), incl = len;
+                    len = min(len, CAP);
+                    incl = len;
                 }
-                if (lane < nfit) {
-                    L.t_src[lane] = src + lo;
-                    L.t_len[lane] = len;
-                    L.t_base[lane] = incl - len;
-                    // a trace without staged samples gets lim = -1: none of its windows count
-                    L.tinfo[lane] = make_int2(incl - len - lo, len > 0 ? nsg - 1 - W : -1);
-                    L.t_cc[lane] = cc;
-                    L.t_dm[lane] = (float)dm;
-                }
-                if (lane == 0) L.nfit = nfit;
-            }
-            __syncthreads();
-            const int nfit = L.nfit;
+                if (wv == 0 && lane < nfit) L.t_off[e] = incl - len - L.t_lo[e];
 
-            // ---- stage the samples and their window energy -------------------
-            // Direct global->LDS loads (global_load_lds_dword): lane l of a wave
-            // fetches element p0 + l of the trace's range into LDS word
-            // base + p0 + l without passing through registers, so every load of
-            // the chunk is in flight at once; the barrier below waits for them.
-            for (int r = wv; r < nfit; r += NW) {
-                const long long src = L.t_src[r];
-                const int len = L.t_len[r], base = L.t_base[r];
-                for (int p0 = 0; p0 < len; p0 += WAVE) {
-                    if (p0 + lane < len) {
-                        const long long gi = src + p0 + lane;
-                        lds_dma(g.samples + gi, &L.lf[base + p0]);
-                        lds_dma(pv.u0 + gi, &L.lu0[base + p0]);
-                        lds_dma(pv.u1 + gi, &L.lu1[base + p0]);
-                        lds_dma(pv.u2sq + gi, &L.lu2[base + p0]);
+                // ---- stage the samples and their window energy -------------------
+                // Direct global->LDS loads (global_load_lds_dword): lane l of a wave
+                // fetches element p0 + l of the trace's range into LDS word
+                // base + p0 + l without passing through registers, so every load of
+                // the chunk is in flight at once; the barrier below waits for them.
+                for (int r = wv; r < nfit; r += NW) {
+                    const int rl = __builtin_amdgcn_readlane(len, r);
+                    const int rb = __builtin_amdgcn_readlane(incl, r) - rl;
+                    const long long src = L.t_base[cb + r] + L.t_lo[cb + r];
+                    for (int p0 = 0; p0 < rl; p0 += WAVE) {
+                        if (p0 + lane < rl) {
+                            const long long gi = src + p0 + lane;
+                            lds_dma(g.samples + gi, &L.lf[rb + p0]);
+                            lds_dma(pv.u0 + gi, &L.lu0[rb + p0]);
+                            lds_dma(pv.u1 + gi, &L.lu1[rb + p0]);
+                            lds_dma(pv.u2sq + gi, &L.lu2[rb + p0]);
+                        }
                     }
                 }
-            }
-            if (CRS) {
-                // per (parameter, trace): num = s u1 + u0 with
-                //   u1 = 2 alpha + beta, u0 = alpha^2 + gamma (FP64)
-                for (int pl = wv; pl < NT; pl += NW) {
-                    if (lane < nfit) {
-                        const double dmr = L.t_dm[lane];
-                        const double al = L.pA[pl] * 2.0 * dmr * inv_dt;
-                        const double be = L.pB[pl] * 2.0 * dmr * dmr * inv_dt;
-                        L.tab[pl][lane] = make_double2(2.0 * al + be, fma(al, al, L.pq[pl] * L.t_cc[lane]));
+                if (CRS) {
+                    // per (parameter, trace): num = s u1 + u0 with
+                    //   u1 = 2 alpha + beta, u0 = alpha^2 + gamma (FP64)
+                    for (int pl = wv; pl < NT; pl += NW) {
+                        if (lane < nfit) {
+                            const double dmr = L.t_dm[e];
+                            const double al = L.pA[pl] * 2.0 * dmr * inv_dt;
+                            const double be = L.pB[pl] * 2.0 * dmr * dmr * inv_dt;
+                            L.tab[pl][lane] = make_double2(2.0 * al + be, fma(al, al, L.pq[pl] * L.t_cc[e]));
+                        }
                     }
                 }
-            }
-            __syncthreads();
+                __syncthreads();
 
-            // ---- the hot loop: traces outer, this lane's P parameters inner ----
-            // First the P intersections (independent FP64 chains), then the P
-            // windows.  In the branch-free form a window that is off the trace
-            // reads a harmless in-range LDS word with zero weights, so the loads
-            // of all P windows can be in flight together.
-            double qd[P];  // this wave's parameters (CMP), held in scalar registers
+                // ---- the hot loop: traces outer, this lane's P parameters inner ----
+                // The valid set is decided on T > 0: T = 0 only arises from
+                // s = 0 with nothing else (handled by s2e above) or exactly on
+                // a CRS surface's edge, a set of measure zero.
+                double qd[P];  // this wave's parameters (CMP), held in scalar registers
 #pragma unroll
-            for (int p = 0; p < P; ++p) qd[p] = to_sgpr(L.pq[wv * P + p]);
-            if (lane_on) {
-                for (int r = 0; r < nfit; ++r) {
-                    const int2 ti = L.tinfo[r];
-                    if (ti.y < 0) continue;  // uniform: no staged window on this trace
-                    const double cc = L.t_cc[r];
-                    int idx[P];
-                    float xw[P], uw[P], vm[P];
+                for (int p = 0; p < P; ++p) qd[p] = to_sgpr(L.pq[wv * P + p]);
+                if (lane_on) {
+                    for (int r = 0; r < nfit; ++r) {
+                        const int lim = L.t_lim[cb + r];
+                        if (lim < 0) continue;  // uniform: no staged window on this trace
+                        const int off = L.t_off[cb + r];
+                        const double cc = L.t_cc[cb + r];
+                        if (BRANCHY) {
 #pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        double num;
-                        if (CRS) {
-                            const double2 tv = L.tab[wv * P + p][r];
-                            num = fma(sd, tv.x, tv.y);
+                            for (int p = 0; p < P; ++p) {
+                                double T;
+                                if (CRS) {
+                                    const double2 tv = L.tab[wv * P + p][r];
+                                    T = s2e + fma(sd, tv.x, tv.y);
+                                } else {
+                                    T = fma(qd[p], cc, s2e);
+                                }
+                                // tau < 2^30 keeps the conversion exact (floor); NaN
+                                // from T <= 0 becomes 2^30, rejected with T below
+                                const double tau = fmin(sqrt_newton(T), 1073741824.0);
+                                const int a = (int)tau - HW;
+                                if (!((unsigned)a <= (unsigned)lim && T > 0.0)) continue;
+                                const float x = (float)__builtin_amdgcn_fract(tau);
+                                const float u = 1.f - x;
+                                const int id = a + off;
+                                float fw[W + 1];
+#pragma unroll
+                                for (int j = 0; j <= W; ++j) fw[j] = L.lf[id + j];
+#pragma unroll
+                                for (int j = 0; j < W; ++j) {
+                                    U[p][j] = fmaf(u, fw[j], U[p][j]);
+                                    U[p][j] = fmaf(x, fw[j + 1], U[p][j]);
+                                }
+                                const float tq = fmaf(x, L.lu1[id], L.lu0[id]);
+                                D[p] += fmaf(tq, tq, L.lu2[id]);
+                                Mc[p] += 1.f;
+                            }
                         } else {
-                            num = qd[p] * cc;
+                            int idx[P];
+                            float xw[P], uw[P], vm[P];
+#pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                double T;
+                                if (CRS) {
+                                    const double2 tv = L.tab[wv * P + p][r];
+                                    T = s2e + fma(sd, tv.x, tv.y);
+                                } else {
+                                    T = fma(qd[p], cc, s2e);
+                                }
+                                const double tau = fmin(sqrt_newton(T), 1073741824.0);
+                                const int a = (int)tau - HW;
+                                const bool ok = (unsigned)a <= (unsigned)lim && T > 0.0;
+                                idx[p] = ok ? a + off : 0;
+                                xw[p] = ok ? (float)__builtin_amdgcn_fract(tau) : 0.f;
+                                vm[p] = ok ? 1.f : 0.f;
+                                uw[p] = vm[p] - xw[p];
+                            }
+                            // a window that is off the trace reads a harmless in-range
+                            // LDS word with zero weights, so the loads of all P windows
+                            // can be in flight together
+#pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                const int id = idx[p];
+                                float fw[W + 1];
+#pragma unroll
+                                for (int j = 0; j <= W; ++j) fw[j] = L.lf[id + j];
+#pragma unroll
+                                for (int j = 0; j < W; ++j) {
+                                    U[p][j] = fmaf(uw[p], fw[j], U[p][j]);
+                                    U[p][j] = fmaf(xw[p], fw[j + 1], U[p][j]);
+                                }
+                                const float tq = fmaf(xw[p], L.lu1[id], L.lu0[id]);
+                                D[p] = fmaf(vm[p], fmaf(tq, tq, L.lu2[id]), D[p]);
+                                Mc[p] += vm[p];
+                            }
                         }
-                        const double T = s2 + num;
-                        const Hit hit = hit_from_tau(sqrt_refined(T), HW);
-                        const bool ok = on_trace(hit.a, ti.y) && T >= 0.0;
-                        idx[p] = ok ? hit.a + ti.x : 0;
-                        xw[p] = ok ? hit.x : 0.f;
-                        vm[p] = ok ? 1.f : 0.f;
-                        uw[p] = vm[p] - xw[p];
-                    }
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        if (BRANCHY && vm[p] == 0.f) continue;
-                        const int id = idx[p];
-                        float fw[W + 1];
-#pragma unroll
-                        for (int j = 0; j <= W; ++j) fw[j] = L.lf[id + j];
-#pragma unroll
-                        for (int j = 0; j < W; ++j) {
-                            U[p][j] = fmaf(uw[p], fw[j], U[p][j]);
-                            U[p][j] = fmaf(xw[p], fw[j + 1], U[p][j]);
-                        }
-                        const float tq = fmaf(xw[p], L.lu1[id], L.lu0[id]);
-                        D[p] = fmaf(vm[p], fmaf(tq, tq, L.lu2[id]), D[p]);
-                        Mc[p] += vm[p];
                     }
                 }
+                __syncthreads();
+                cb += nfit;
             }
-            __syncthreads();
-            t0 += nfit;
         }
 
         // ---- semblance of this block's parameters; running pick --------------
@@ -471,21 +552,21 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
     }
 }
 
-// Tile shapes (measured on MI355X, see the design notes).  CMP: 4 parameters
-// per lane in 4 waves at <= 128 VGPRs (4 waves per SIMD), 2048-position
-// stage, windows behind a branch.  CRS, whose per-evaluation table read and
-// wider apertures favour occupancy: 2 parameters per lane in 8 waves,
-// 3072-position stage, branch-free windows.
+// Tile shapes (measured on MI355X).  CMP: 4 parameters per lane in 4 waves
+// at <= 128 VGPRs (4 waves per SIMD), 2048-position stage, windows behind a
+// branch, metadata of up to 128 traces.  CRS, whose per-evaluation table
+// read and wider apertures favour occupancy: 2 parameters per lane in 8
+// waves, 3072-position stage, branch-free windows, up to 256 traces.
 template <int KIND, int W>
 struct Shape;
 template <int W>
 struct Shape<SEMB_KIND_CMP, W> {
-    static constexpr int NW = 4, P = W <= 15 ? 4 : 2, CAP = 2048, WPE = 4;
+    static constexpr int NW = 4, P = W <= 15 ? 4 : 2, CAP = 2048, WPE = 4, TMAX = 128;
     static constexpr bool BRANCHY = true;
 };
 template <int W>
 struct Shape<SEMB_KIND_CRS, W> {
-    static constexpr int NW = 8, P = 2, CAP = 3072, WPE = 1;
+    static constexpr int NW = 8, P = 2, CAP = 3072, WPE = 1, TMAX = 256;
     static constexpr bool BRANCHY = false;
 };
 
@@ -496,7 +577,7 @@ __attribute__((amdgpu_waves_per_eu(Shape<KIND, W>::WPE)))
 scan_kernel(ScanArgs a)
 {
     using S = Shape<KIND, W>;
-    __shared__ StageLds<KIND, W, S::P, S::NW, S::CAP> L;
+    __shared__ StageLds<KIND, W, S::P, S::NW, S::CAP, S::TMAX> L;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int job = tile / a.j.n_sblk;
     const int sblk = tile - job * a.j.n_sblk;
@@ -504,8 +585,8 @@ scan_kernel(ScanArgs a)
     if (sblk * WAVE >= a.g.ns[a.j.central[job]]) return;  // uniform, before any barrier
     float bS, bSt;
     int bI;
-    scan_tile<KIND, W, S::P, S::NW, S::CAP, S::BRANCHY>(a.g, a.j, a.p, L, job, sblk, 0, a.p.npar, a.panel,
-                                                          bS, bI, bSt);
+    scan_tile<KIND, W, S::P, S::NW, S::CAP, S::TMAX, S::BRANCHY>(a.g, a.j, a.p, L, job, sblk, 0, a.p.npar,
+                                                                   a.panel, bS, bI, bSt);
     const int lane = threadIdx.x & (WAVE - 1);
     if (threadIdx.x < WAVE && bS >= 0.f) {
         const int64_t row = a.j.out_off[job] + sblk * WAVE + lane;
@@ -561,6 +642,7 @@ constexpr int BATCH_NW = 8;
 constexpr int BATCH_P_CMP = 2;
 constexpr int BATCH_P_CRS = 2;
 constexpr int BATCH_CAP = 3072;
+constexpr int BATCH_TMAX = 256;
 
 __global__ void reset_counters_kernel(unsigned int *c, int n)
 {
@@ -571,8 +653,8 @@ template <int WC, int WR>
 __global__ void __launch_bounds__(BATCH_NW * WAVE) __attribute__((amdgpu_waves_per_eu(4)))
 batch_kernel(BatchArgs b)
 {
-    using LC = StageLds<SEMB_KIND_CMP, WC, BATCH_P_CMP, BATCH_NW, BATCH_CAP>;
-    using LR = StageLds<SEMB_KIND_CRS, WR, BATCH_P_CRS, BATCH_NW, BATCH_CAP>;
+    using LC = StageLds<SEMB_KIND_CMP, WC, BATCH_P_CMP, BATCH_NW, BATCH_CAP, BATCH_TMAX>;
+    using LR = StageLds<SEMB_KIND_CRS, WR, BATCH_P_CRS, BATCH_NW, BATCH_CAP, BATCH_TMAX>;
     __shared__ union U {
         LC c;
         LR r;
@@ -592,10 +674,10 @@ batch_kernel(BatchArgs b)
         float bS, bSt;
         int bI;
         if (kind == SEMB_KIND_CMP)
-            scan_tile<SEMB_KIND_CMP, WC, BATCH_P_CMP, BATCH_NW, BATCH_CAP, true>(
+            scan_tile<SEMB_KIND_CMP, WC, BATCH_P_CMP, BATCH_NW, BATCH_CAP, BATCH_TMAX, true>(
                 b.g, b.j, b.pc, L.c, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, bS, bI, bSt);
         else
-            scan_tile<SEMB_KIND_CRS, WR, BATCH_P_CRS, BATCH_NW, BATCH_CAP, false>(
+            scan_tile<SEMB_KIND_CRS, WR, BATCH_P_CRS, BATCH_NW, BATCH_CAP, BATCH_TMAX, false>(
                 b.g, b.j, b.pr, L.r, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, bS, bI, bSt);
         const int64_t row = b.j.out_off[tl.job] + tl.sblk * WAVE + lane;
         if (tl.nsplit <= 1) {

@@ -29,6 +29,17 @@ __device__ __forceinline__ double sqrt_refined(double T)
     return fma(r, 0.5 * y, t0);
 }
 
+// The scan's form: sqrt(T) for T > 0 by the same reciprocal square root and
+// Newton step, without the clamp.  For T <= 0 the result is NaN or infinite;
+// the scan rejects those T itself and clamps the result before converting it.
+__device__ __forceinline__ double sqrt_newton(double T)
+{
+    const double y = __builtin_amdgcn_rsq(T);
+    const double t0 = T * y;
+    const double r = fma(-t0, t0, T);
+    return fma(r, 0.5 * y, t0);
+}
+
 // Window start a = floor(tau) - hw and fraction x of one intersection, tau >= 0.
 struct Hit {
     int a;
