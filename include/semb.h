@@ -266,6 +266,47 @@ semb_status scan_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_
                        const semb_tile *tiles, int64_t ntiles, int32_t ngroups, int32_t nparts,
                        const semb_outputs *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Tile shapes of the exhaustive scan and their tuner.  cmp_scan and crs_scan
+ * are built in SEMB_SCAN_SHAPES tile shapes (waves per workgroup, parameters
+ * per lane, LDS stage size, windows behind a branch or branch-free; every
+ * shape gives bit-identical results).  Which one a call uses is looked up
+ * per (kind, w, traces per job, samples per trace), the two sizes rounded up
+ * to powers of two from the host fields ntraces / ngathers (times max_apert
+ * for CRS) and ns_max; without an entry the kind's default is used (shape 0
+ * for CMP, 1 for CRS).  The table is process-wide and guarded by a mutex.
+ * Tuned tile shapes are the counterpart of the paper's tuning of its tile and
+ * prefetch sizes to the local store (section 3.3, Eq. (2)).
+ * ------------------------------------------------------------------------- */
+#define SEMB_SCAN_SHAPES 4
+
+/* Human-readable description of a shape, NULL if out of range. [host] */
+const char *semb_shape_name(int32_t shape);
+
+/* Times every shape on the first min(sample_jobs, njobs) jobs (one warm-up
+ * and `reps` timed calls each), compares each shape's best / s_best / stack
+ * rows of those jobs with the default shape's, and records the fastest shape
+ * whose rows are bit-identical for this call's key; *shape receives it,
+ * ms[SEMB_SCAN_SHAPES] (nullable, host) each shape's mean time per call in
+ * milliseconds, or -1 for a shape whose outputs differed.  Arguments as for
+ * cmp_scan (kind CMP; A, B ignored) or crs_scan; the sampled jobs' output
+ * rows are overwritten.  Synchronizes `stream`: not for graph capture. */
+semb_status semb_tune_scan(const semb_gathers *g, const semb_jobs *jobs, int32_t kind, const float *A,
+                           int32_t nA, const float *B, int32_t nB, const float *q, int32_t nq, int32_t w,
+                           int32_t sample_jobs, int32_t reps, const semb_outputs *out, void *ws,
+                           size_t ws_bytes, int32_t *shape, float *ms, hipStream_t stream);
+
+/* Record `shape` for the key of (kind, w, g, jobs); -1 removes the entry.
+ * Reads only host fields of g and jobs. [host] */
+semb_status semb_set_scan_shape(int32_t kind, int32_t w, const semb_gathers *g, const semb_jobs *jobs,
+                                int32_t shape);
+
+/* The shape a scan with these arguments uses (-1 for invalid arguments). [host] */
+int32_t semb_scan_shape(int32_t kind, int32_t w, const semb_gathers *g, const semb_jobs *jobs);
+
+/* Forget every recorded shape. [host] */
+void semb_clear_tuning(void);
+
 /* Kernel timing for measurement.  After semb_kernel_timer_start(capacity),
  * the next `capacity` launches of a call's main kernel made by this thread
  * (the scan kernel of cmp_scan / crs_scan, the persistent kernel of

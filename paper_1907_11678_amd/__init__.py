@@ -106,6 +106,16 @@ def lib():
         L.semb_refine.restype = C.c_int
         L.semb_theta_from_best.argtypes = [P, i64, P, i32, P, i32, P, i32, P, P]
         L.semb_theta_from_best.restype = C.c_int
+        L.semb_shape_name.argtypes = [i32]
+        L.semb_shape_name.restype = C.c_char_p
+        L.semb_tune_scan.argtypes = [P, P, i32, P, i32, P, i32, P, i32, i32, i32, i32, P, P, C.c_size_t, P, P, P]
+        L.semb_tune_scan.restype = C.c_int
+        L.semb_set_scan_shape.argtypes = [i32, i32, P, P, i32]
+        L.semb_set_scan_shape.restype = C.c_int
+        L.semb_scan_shape.argtypes = [i32, i32, P, P]
+        L.semb_scan_shape.restype = i32
+        L.semb_clear_tuning.argtypes = []
+        L.semb_clear_tuning.restype = None
         L.semb_kernel_timer_start.argtypes = [i32]
         L.semb_kernel_timer_start.restype = C.c_int
         L.semb_kernel_timer_stop.argtypes = [P, P, i32]
@@ -334,6 +344,52 @@ def alloc_workspace(nsamples: int, device="cuda"):
     ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
     off = (-ws.data_ptr()) % 256
     return ws[off:off + nbytes]
+
+
+# ---------------------------------------------------------------------------
+# tile shapes of the exhaustive scan and their tuner
+# ---------------------------------------------------------------------------
+SCAN_SHAPES = 4
+
+
+def shape_name(shape: int) -> str | None:
+    r = lib().semb_shape_name(int(shape))
+    return None if r is None else r.decode()
+
+
+def tune_scan(kind: int, g: DeviceGathers, jobs: DeviceJobs, q, w: int, best, s_best, stack_out, ws,
+              A=None, B=None, sample_jobs: int = 256, reps: int = 2, stream=None):
+    """Time every tile shape on the first `sample_jobs` jobs, record the fastest
+    whose outputs equal the default shape's, and return (shape, [ms per shape]
+    with -1 for excluded shapes).  Synchronizes the stream."""
+    import torch
+    gs, js, out = g.cstruct(), jobs.cstruct(), _outputs(best, s_best, stack_out, None)
+    shape = C.c_int32(-1)
+    ms = (C.c_float * SCAN_SHAPES)()
+    nA = int(A.numel()) if A is not None else 1
+    nB = int(B.numel()) if B is not None else 1
+    _check(lib().semb_tune_scan(C.byref(gs), C.byref(js), int(kind),
+                                _typed(A, torch.float32, "A") if A is not None else None, nA,
+                                _typed(B, torch.float32, "B") if B is not None else None, nB,
+                                _typed(q, torch.float32, "q"), int(q.numel()), int(w), int(sample_jobs),
+                                int(reps), C.byref(out), _ptr(ws), int(ws.numel() * ws.element_size()),
+                                C.byref(shape), ms, _stream(stream)))
+    return int(shape.value), [float(x) for x in ms]
+
+
+def set_scan_shape(kind: int, w: int, g: DeviceGathers, jobs: DeviceJobs, shape: int):
+    """Use `shape` (-1: back to the tuned/default choice) for scans with this key."""
+    gs, js = g.cstruct(), jobs.cstruct()
+    _check(lib().semb_set_scan_shape(int(kind), int(w), C.byref(gs), C.byref(js), int(shape)))
+
+
+def scan_shape(kind: int, w: int, g: DeviceGathers, jobs: DeviceJobs) -> int:
+    gs, js = g.cstruct(), jobs.cstruct()
+    return int(lib().semb_scan_shape(int(kind), int(w), C.byref(gs), C.byref(js)))
+
+
+def clear_tuning():
+    lib().semb_clear_tuning()
 
 
 # ---------------------------------------------------------------------------

@@ -5,9 +5,13 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
@@ -155,9 +159,54 @@ semb::JobView job_view(const semb_jobs *jobs, const semb_gathers *g, bool crs)
     return v;
 }
 
+// ---- tile shapes of the exhaustive scan and the tuner's choices ------------
+// The choice is kept per (kind, window, traces per job, samples per trace),
+// the two sizes as powers-of-two buckets computed from host-side fields.
+struct ShapeKey {
+    int kind, w, traces, ns;
+    bool operator<(const ShapeKey &o) const
+    {
+        return std::tie(kind, w, traces, ns) < std::tie(o.kind, o.w, o.traces, o.ns);
+    }
+};
+
+std::mutex g_shape_mu;
+std::map<ShapeKey, int> g_shapes;
+
+int log2_bucket(double v)
+{
+    int b = 0;
+    while (b < 40 && (double)(1LL << b) < v) ++b;
+    return b;
+}
+
+ShapeKey shape_key(int kind, int w, const semb_gathers *g, const semb_jobs *jobs)
+{
+    const double fold = g->ngathers > 0 ? (double)g->ntraces / g->ngathers : 0.0;
+    const double apert = kind == SEMB_KIND_CRS ? (double)std::max(1, jobs->max_apert) : 1.0;
+    return ShapeKey{kind, w, log2_bucket(fold * apert), log2_bucket(g->ns_max)};
+}
+
+int default_shape(int kind) { return kind == SEMB_KIND_CRS ? 1 : 0; }
+
+int chosen_shape(int kind, int w, const semb_gathers *g, const semb_jobs *jobs)
+{
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    const auto it = g_shapes.find(shape_key(kind, w, g, jobs));
+    return it == g_shapes.end() ? default_shape(kind) : it->second;
+}
+
+const char *const kShapeNames[semb::kScanShapes] = {
+    "4 waves x 4 parameters (2 for w > 15), 2048-sample stage, windows behind a branch",
+    "8 waves x 2 parameters, 3072-sample stage, branch-free windows",
+    "8 waves x 2 parameters, 3072-sample stage, windows behind a branch",
+    "4 waves x 4 parameters (2 for w > 15), 2048-sample stage, branch-free windows",
+};
+
+// shape < 0: the tuned (or default) shape for this call's key
 semb_status scan_common(int kind, const semb_gathers *g, const semb_jobs *jobs, const float *A, int32_t nA,
                         const float *B, int32_t nB, const float *q, int32_t nq, int32_t w,
-                        const semb_outputs *out, void *ws, size_t ws_bytes, hipStream_t stream)
+                        const semb_outputs *out, void *ws, size_t ws_bytes, hipStream_t stream, int shape = -1)
 {
     const bool crs = kind == SEMB_KIND_CRS;
     TRY(check_gathers(g, crs));
@@ -203,7 +252,8 @@ semb_status scan_common(int kind, const semb_gathers *g, const semb_jobs *jobs, 
     a.s_best = out->s_best;
     a.stack = out->stack;
     a.panel = out->panel;
-    return hip_status(timed(stream, [&] { return semb::launch_scan(kind, a, stream); }),
+    const int sid = shape >= 0 ? shape : chosen_shape(kind, w, g, jobs);
+    return hip_status(timed(stream, [&] { return semb::launch_scan(kind, a, sid, stream); }),
                       crs ? "crs_scan launch" : "cmp_scan launch");
 }
 
@@ -553,6 +603,138 @@ semb_status semb_kernel_timer_stop(int32_t *count, float *ms, int32_t ms_len)
     }
     t.release();
     return st;
+}
+
+const char *semb_shape_name(int32_t shape)
+{
+    return (shape >= 0 && shape < semb::kScanShapes) ? kShapeNames[shape] : nullptr;
+}
+
+semb_status semb_set_scan_shape(int32_t kind, int32_t w, const semb_gathers *g, const semb_jobs *jobs,
+                                int32_t shape)
+{
+    if ((kind != SEMB_KIND_CMP && kind != SEMB_KIND_CRS) || !g || !jobs)
+        return fail(SEMB_EINVAL, "semb_set_scan_shape: kind must be CMP or CRS, g and jobs non-NULL");
+    if (shape < -1 || shape >= semb::kScanShapes)
+        return fail(SEMB_EINVAL, "semb_set_scan_shape: shape must be -1 .. %d", semb::kScanShapes - 1);
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    const ShapeKey key = shape_key(kind, w, g, jobs);
+    if (shape < 0)
+        g_shapes.erase(key);
+    else
+        g_shapes[key] = shape;
+    return SEMB_OK;
+}
+
+int32_t semb_scan_shape(int32_t kind, int32_t w, const semb_gathers *g, const semb_jobs *jobs)
+{
+    if ((kind != SEMB_KIND_CMP && kind != SEMB_KIND_CRS) || !g || !jobs) return -1;
+    return chosen_shape(kind, w, g, jobs);
+}
+
+void semb_clear_tuning(void)
+{
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shapes.clear();
+}
+
+semb_status semb_tune_scan(const semb_gathers *g, const semb_jobs *jobs, int32_t kind, const float *A, int32_t nA,
+                           const float *B, int32_t nB, const float *q, int32_t nq, int32_t w, int32_t sample_jobs,
+                           int32_t reps, const semb_outputs *out, void *ws, size_t ws_bytes, int32_t *shape,
+                           float *ms, hipStream_t stream)
+{
+    if (kind != SEMB_KIND_CMP && kind != SEMB_KIND_CRS) return fail(SEMB_EINVAL, "kind must be CMP or CRS");
+    if (!shape || sample_jobs < 1 || reps < 1)
+        return fail(SEMB_EINVAL, "semb_tune_scan: shape must be non-NULL, sample_jobs and reps >= 1");
+    const bool crs = kind == SEMB_KIND_CRS;
+    TRY(check_gathers(g, crs));
+    TRY(check_jobs(jobs, crs, g));
+    semb_jobs sub = *jobs;
+    sub.njobs = std::min(sample_jobs, jobs->njobs);
+    for (int s = 0; s < semb::kScanShapes && ms; ++s) ms[s] = -1.f;
+    *shape = chosen_shape(kind, w, g, jobs);
+    if (sub.njobs == 0) return SEMB_OK;
+    // a first call validates every argument the same way the scans do
+    TRY(scan_common(kind, g, &sub, A, nA, B, nB, q, nq, w, out, ws, ws_bytes, stream, default_shape(kind)));
+
+    // the sampled jobs' output rows, on the host
+    std::vector<int64_t> off(sub.njobs);
+    std::vector<int32_t> cen(sub.njobs), nsv(g->ngathers);
+    TRY(hip_status(hipMemcpyAsync(off.data(), jobs->out_off, sizeof(int64_t) * sub.njobs, hipMemcpyDeviceToHost,
+                                  stream), "semb_tune_scan: copy"));
+    TRY(hip_status(hipMemcpyAsync(cen.data(), jobs->central, sizeof(int32_t) * sub.njobs, hipMemcpyDeviceToHost,
+                                  stream), "semb_tune_scan: copy"));
+    TRY(hip_status(hipMemcpyAsync(nsv.data(), g->ns, sizeof(int32_t) * g->ngathers, hipMemcpyDeviceToHost, stream),
+                   "semb_tune_scan: copy"));
+    TRY(hip_status(hipStreamSynchronize(stream), "semb_tune_scan: synchronize"));
+    size_t nrows = 0;
+    for (int j = 0; j < sub.njobs; ++j) nrows += (size_t)std::max(0, nsv[cen[j]]);
+    auto fetch = [&](std::vector<int32_t> &b, std::vector<float> &sb, std::vector<float> &st) -> semb_status {
+        b.resize(nrows);
+        sb.resize(nrows);
+        st.resize(nrows);
+        size_t at = 0;
+        for (int j = 0; j < sub.njobs; ++j) {
+            const size_t n = (size_t)std::max(0, nsv[cen[j]]);
+            if (n == 0) continue;
+            TRY(hip_status(hipMemcpyAsync(&b[at], out->best + off[j], 4 * n, hipMemcpyDeviceToHost, stream), "copy"));
+            TRY(hip_status(hipMemcpyAsync(&sb[at], out->s_best + off[j], 4 * n, hipMemcpyDeviceToHost, stream),
+                           "copy"));
+            TRY(hip_status(hipMemcpyAsync(&st[at], out->stack + off[j], 4 * n, hipMemcpyDeviceToHost, stream),
+                           "copy"));
+            at += n;
+        }
+        return hip_status(hipStreamSynchronize(stream), "semb_tune_scan: synchronize");
+    };
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TRY(hip_status(hipEventCreate(&e0), "hipEventCreate"));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SEMB_EHIP, "hipEventCreate failed");
+    }
+    semb_status st = SEMB_OK;
+    std::vector<int32_t> rb, cb;
+    std::vector<float> rs, rt, cs, ct;
+    int best_shape = default_shape(kind);
+    float best_ms = 0.f;
+    const int d = default_shape(kind);
+    for (int k = 0; k < semb::kScanShapes && st == SEMB_OK; ++k) {
+        const int sid = k == 0 ? d : (k <= d ? k - 1 : k);  // the default first
+        st = scan_common(kind, g, &sub, A, nA, B, nB, q, nq, w, out, ws, ws_bytes, stream, sid);  // warm-up
+        if (st == SEMB_OK) st = hip_status(hipEventRecord(e0, stream), "hipEventRecord");
+        for (int r = 0; r < reps && st == SEMB_OK; ++r)
+            st = scan_common(kind, g, &sub, A, nA, B, nB, q, nq, w, out, ws, ws_bytes, stream, sid);
+        if (st == SEMB_OK) st = hip_status(hipEventRecord(e1, stream), "hipEventRecord");
+        if (st == SEMB_OK) st = hip_status(hipEventSynchronize(e1), "hipEventSynchronize");
+        float t = 0.f;
+        if (st == SEMB_OK) st = hip_status(hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime");
+        if (st != SEMB_OK) break;
+        t /= (float)reps;
+        bool same = true;
+        if (k == 0) {
+            st = fetch(rb, rs, rt);
+        } else {
+            st = fetch(cb, cs, ct);
+            same = cb == rb && memcmp(cs.data(), rs.data(), 4 * nrows) == 0 &&
+                   memcmp(ct.data(), rt.data(), 4 * nrows) == 0;
+        }
+        if (st != SEMB_OK) break;
+        if (ms) ms[sid] = same ? t : -1.f;
+        if (same && (k == 0 || t < best_ms)) {
+            best_ms = t;
+            best_shape = sid;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SEMB_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_shape_mu);
+        g_shapes[shape_key(kind, w, g, jobs)] = best_shape;
+    }
+    *shape = best_shape;
+    return SEMB_OK;
 }
 
 const char *semb_last_error(void) { return g_last_error.c_str(); }

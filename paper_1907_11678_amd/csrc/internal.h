@@ -118,7 +118,11 @@ hipError_t launch_window_energy(const float *samples, const int64_t *sample_off,
                                 const int32_t *trace_ptr, const int32_t *ns, int32_t ngathers,
                                 int32_t ntraces, int32_t w, float *u0, float *u1, float *u2sq,
                                 hipStream_t stream);
-hipError_t launch_scan(int kind, const ScanArgs &a, hipStream_t stream);
+// Exhaustive scan in tile shape `shape` (0 .. kScanShapes - 1).
+constexpr int kScanShapes = 4;
+hipError_t launch_scan(int kind, const ScanArgs &a, int shape, hipStream_t stream);
+hipError_t launch_scan_cmp(const ScanArgs &a, int shape, hipStream_t stream);
+hipError_t launch_scan_crs(const ScanArgs &a, int shape, hipStream_t stream);
 hipError_t launch_batch(const BatchArgs &a, int ngroups, hipStream_t stream);
 hipError_t launch_point(int kind, const PointArgs &a, hipStream_t stream);
 hipError_t launch_grad(int kind, const PointArgs &a, hipStream_t stream);

@@ -174,3 +174,38 @@ def test_batch_plan_rejects_bad_input(semb):
     with pytest.raises(semb.SembError):
         semb.batch_plan(np.array([0], np.int32), np.array([3], np.int32), np.array([0, 1], np.int32),
                         np.array([0], np.int32), np.array([10], np.int32), np.array([0, 1], np.int32), 5, 5)
+
+
+def test_shape_names_and_host_side_table(semb):
+    L = semb.lib()
+    for s in range(semb.SCAN_SHAPES):
+        assert semb.shape_name(s)
+    assert semb.shape_name(semb.SCAN_SHAPES) is None and semb.shape_name(-1) is None
+    g = _gathers(semb, ntraces=600, ngathers=20, ns_max=1000)
+    j = _jobs(semb, max_apert=9)
+    L.semb_clear_tuning()
+    assert L.semb_scan_shape(0, 11, C.byref(g), C.byref(j)) == 0
+    assert L.semb_scan_shape(1, 11, C.byref(g), C.byref(j)) == 1
+    assert L.semb_set_scan_shape(1, 11, C.byref(g), C.byref(j), 3) == 0
+    assert L.semb_scan_shape(1, 11, C.byref(g), C.byref(j)) == 3
+    g2 = _gathers(semb, ntraces=600, ngathers=20, ns_max=1900)  # another ns bucket
+    assert L.semb_scan_shape(1, 11, C.byref(g2), C.byref(j)) == 1
+    assert L.semb_scan_shape(1, 9, C.byref(g), C.byref(j)) == 1   # other window
+    assert L.semb_set_scan_shape(1, 11, C.byref(g), C.byref(j), 4) == 1
+    assert L.semb_set_scan_shape(2, 11, C.byref(g), C.byref(j), 0) == 1
+    assert L.semb_set_scan_shape(1, 11, C.byref(g), C.byref(j), -1) == 0
+    assert L.semb_scan_shape(1, 11, C.byref(g), C.byref(j)) == 1
+    L.semb_clear_tuning()
+
+
+def test_tuner_rejects_bad_arguments(semb):
+    L = semb.lib()
+    g, j, out = _gathers(semb), _jobs(semb), _outs(semb)
+    shape = C.c_int32(0)
+    P = C.c_void_p(0x4000)
+    assert L.semb_tune_scan(C.byref(g), C.byref(j), 0, None, 1, None, 1, P, 8, 11, 0, 1, C.byref(out),
+                            C.c_void_p(0x10000), 1 << 20, C.byref(shape), None, None) == 1
+    assert L.semb_tune_scan(C.byref(g), C.byref(j), 0, None, 1, None, 1, P, 8, 11, 4, 1, C.byref(out),
+                            C.c_void_p(0x10000), 1 << 20, None, None, None) == 1
+    assert L.semb_tune_scan(C.byref(g), C.byref(j), 5, None, 1, None, 1, P, 8, 11, 4, 1, C.byref(out),
+                            C.c_void_p(0x10000), 1 << 20, C.byref(shape), None, None) == 1

@@ -1,0 +1,114 @@
+"""GPU tests of the scan's tile shapes and their tuner: every shape must give
+the default shape's outputs bit for bit (the tuner relies on it, and so does
+every parity claim made with the default), a non-default shape must match the
+oracle, and the tuner must record the shape it picks."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import gpu_util as gu
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+KIND = {"cmp": 0, "crs": 1}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1907_11678_amd as semb
+    semb.lib()
+    torch.cuda.set_device(0)
+    oracle.set_fragility(gu.FRAGILE_TAU, gu.FRAGILE_T_REL)
+    yield
+    semb.clear_tuning()
+    oracle.set_fragility(*oracle.FRAGILE_DEFAULT)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _ragged(kind, w):
+    rng = np.random.default_rng(300 + w)
+    if kind == "cmp":
+        gs = helpers.random_line(rng, 7, fold_range=(1, 9), ns_range=(20, 700), hmax=900.0, smooth=True)
+        return gs, synth.cmp_jobs(gs), synth.Grid(q=synth.velocity_grid(700, 3000, 37))
+    gs = helpers.random_line(rng, 9, fold_range=(1, 6), ns_range=(30, 400), hmax=400.0, smooth=True)
+    grid = synth.Grid(A=np.array([-3e-3, -5e-4, 0.0, 2e-3], np.float32),
+                      B=np.array([-2e-5, -1e-6, 0.0, 1e-5], np.float32),
+                      q=synth.velocity_grid(700, 3000, 7))
+    return gs, synth.line_crs_jobs(gs, list(range(9)), 2), grid
+
+
+@pytest.mark.parametrize("kind", ["cmp", "crs"])
+@pytest.mark.parametrize("w", [1, 9, 15, 31])
+def test_every_shape_equals_the_default(kind, w):
+    import paper_1907_11678_amd as semb
+    gs, jobs, grid = _ragged(kind, w)
+    dg, dj = gu.device_inputs(gs, jobs)
+    semb.set_scan_shape(KIND[kind], w, dg, dj, -1)
+    ref = gu.run_scan(kind, gs, jobs, grid, w, panel=True, dg=dg, dj=dj)
+    try:
+        for shape in range(semb.SCAN_SHAPES):
+            semb.set_scan_shape(KIND[kind], w, dg, dj, shape)
+            assert semb.scan_shape(KIND[kind], w, dg, dj) == shape
+            got = gu.run_scan(kind, gs, jobs, grid, w, panel=True, dg=dg, dj=dj)
+            for a, b, what in zip(got, ref, ("best", "s_best", "stack", "panel")):
+                assert np.array_equal(a, b, equal_nan=True), f"{kind} w={w} shape {shape}: {what} differs"
+    finally:
+        semb.set_scan_shape(KIND[kind], w, dg, dj, -1)
+
+
+@pytest.mark.parametrize("kind,shape", [("cmp", 1), ("cmp", 3), ("crs", 0), ("crs", 2)])
+def test_non_default_shape_matches_oracle(kind, shape):
+    import paper_1907_11678_amd as semb
+    if kind == "cmp":
+        wl = synth.cmp_plain(ids=[5, 6])
+    else:
+        wl = synth.crs_line(centrals=[140], grid=synth.crs_coarse_grid())
+    dg, dj = gu.device_inputs(wl.gathers, wl.jobs)
+    semb.set_scan_shape(KIND[kind], wl.w, dg, dj, shape)
+    try:
+        gpu = gu.run_scan(kind, wl.gathers, wl.jobs, wl.grid, wl.w, dg=dg, dj=dj)
+    finally:
+        semb.set_scan_shape(KIND[kind], wl.w, dg, dj, -1)
+    ref = oracle.scan(kind, wl.gathers, wl.jobs, wl.grid, wl.w)
+    _say(kind, "shape", shape, gu.compare(f"{kind} shape {shape}", gpu, ref,
+                                          gu.sample_scale(wl.gathers, wl.jobs)))
+
+
+def test_tuner_records_its_choice():
+    import torch
+    import paper_1907_11678_amd as semb
+    wl = synth.cmp_plain(ids=list(range(16)))
+    gs, jobs = wl.gathers, wl.jobs
+    dg, dj = gu.device_inputs(gs, jobs)
+    n = jobs.n_out
+    best = torch.empty(n, dtype=torch.int32, device="cuda")
+    sb = torch.empty(n, device="cuda")
+    st = torch.empty(n, device="cuda")
+    ws = semb.alloc_workspace(dg.nsamples)
+    q = torch.from_numpy(wl.grid.q).cuda()
+    semb.clear_tuning()
+    assert semb.scan_shape(0, wl.w, dg, dj) == 0  # the CMP default
+    shape, ms = semb.tune_scan(0, dg, dj, q, wl.w, best, sb, st, ws, sample_jobs=8, reps=2)
+    _say("tuned shape", shape, semb.shape_name(shape), ms)
+    assert 0 <= shape < semb.SCAN_SHAPES
+    assert ms[shape] >= 0 and ms[0] >= 0
+    assert all(m < 0 or m >= ms[shape] for m in ms)
+    assert semb.scan_shape(0, wl.w, dg, dj) == shape
+    # the tuned scan still agrees with the oracle
+    semb.cmp_scan(dg, dj, q, wl.w, best, sb, st, ws)
+    torch.cuda.synchronize()
+    ref = oracle.scan("cmp", gs, jobs, wl.grid, wl.w)
+    gu.compare("tuned", (best.cpu().numpy(), sb.cpu().numpy().astype(np.float64),
+                         st.cpu().numpy().astype(np.float64), None), ref, gu.sample_scale(gs, jobs))
+    semb.clear_tuning()
+    assert semb.scan_shape(0, wl.w, dg, dj) == 0
