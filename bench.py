@@ -185,6 +185,11 @@ def main():
     valid = cmp_valid_evals(h, q_host, NS, gs.dt, W)
     flops = eq2_flops(evals, valid, W)
 
+    # tile shape: tuned on the first 1024 midpoints (outside the timed region)
+    shape, shape_ms = semb.tune_scan(0, dg, dj, q, W, best, sb, st, ws, sample_jobs=1024, reps=2,
+                                     stream=stream)
+    log(f"tile shape {shape} ({semb.shape_name(shape)}); per-shape ms on the sample {shape_ms}")
+
     def step():
         semb.cmp_scan(dg, dj, q, W, best, sb, st, ws, stream=stream)
 
@@ -224,6 +229,7 @@ def main():
                         "201 velocities 1400-5000 m/s, window 15",
             "midpoints": G, "fold": F, "samples": NS, "params": int(q_host.size), "window": W,
             "evals_per_step": evals, "valid_windows_per_step": valid,
+            "tile_shape": shape, "tile_shape_ms_on_sample": shape_ms,
         },
         "roofline": {
             "bound": "alu",
@@ -232,7 +238,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": traffic,
-            "kernel": "scan_kernel<CMP, w=15>",
+            "kernel": f"scan_kernel<CMP, w=15, shape {shape}>",
             "flops_per_launch": flops,
             "avg_launch_ms": k_avg * 1e3,
             "algorithmic_bytes_per_launch": 4 * (gs.samples.size + h.size + 3 * n),
@@ -305,6 +311,8 @@ def crs_leg(torch, synth, semb, dev, stream):
     st = torch.empty(n, dtype=torch.float32, device=dev)
     ws = semb.alloc_workspace(dg.nsamples)
     A, B, q = (torch.from_numpy(x).to(dev) for x in (wl.grid.A, wl.grid.B, wl.grid.q))
+    shape, _ = semb.tune_scan(1, dg, dj, q, wl.w, best, sb, st, ws, A=A, B=B, sample_jobs=32, reps=1,
+                              stream=stream)
     semb.crs_scan(dg, dj, A, B, q, wl.w, best, sb, st, ws, stream=stream)
     torch.cuda.synchronize()
     with semb.KernelTimer(2) as kt:
@@ -323,9 +331,9 @@ def crs_leg(torch, synth, semb, dev, stream):
     res = {"workload": "crs_line: 512 centrals, +-4 gathers x fold 30 (270 traces), 1000 samples (dt 4 ms), "
                        "21x21x41 parameters, window 9",
            "value": evals / wall, "unit": "evals/s", "ms_per_call": wall * 1e3, "evals": evals,
-           "kernel_ms": k_ms, "valid_fraction_16_centrals": vf,
+           "kernel_ms": k_ms, "valid_fraction_16_centrals": vf, "tile_shape": shape,
            "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                        "frac": tflops / PEAK_FP32_TFLOPS, "kernel": "scan_kernel<CRS, w=9>"}}
+                        "frac": tflops / PEAK_FP32_TFLOPS, "kernel": f"scan_kernel<CRS, w=9, shape {shape}>"}}
     fine = {"wl": wl, "dg": dg, "dj": dj, "s_best": sb.cpu().numpy().astype(np.float64), "ms": wall * 1e3}
     return res, fine
 
@@ -352,6 +360,7 @@ def refine_leg(torch, synth, semb, dev, stream, fine):
     hi = (float(coarse.A.max()), float(coarse.B.max()), float(coarse.q.max()))
 
     s = torch.cuda.Stream()
+    shape, _ = semb.tune_scan(1, dg, dj, q, wl.w, best, s0, st0, ws, A=A, B=B, sample_jobs=64, reps=1, stream=s)
 
     def run():
         semb.crs_scan(dg, dj, A, B, q, wl.w, best, s0, st0, ws, stream=s)
@@ -375,7 +384,7 @@ def refine_leg(torch, synth, semb, dev, stream, fine):
     sel = Sf > 0.1
     d = (Sr - Sf)[sel]
     res = {"workload": "crs_line data, coarse 7x7x11 scan + 8 ascent steps per output sample, one HIP graph",
-           "ms": t_ms, "exhaustive_ms": fine["ms"], "speedup_vs_exhaustive": fine["ms"] / t_ms,
+           "ms": t_ms, "coarse_tile_shape": shape, "exhaustive_ms": fine["ms"], "speedup_vs_exhaustive": fine["ms"] / t_ms,
            "rows_compared": int(sel.sum()),
            "s_gap_median": float(np.median(d)), "s_gap_p5": float(np.percentile(d, 5)),
            "frac_at_least_fine": float((d >= -1e-4).mean()),

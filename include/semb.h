@@ -166,6 +166,7 @@ semb_status semblance_grad(const semb_gathers *g, const semb_jobs *jobs, int32_t
 typedef struct semb_refine_opts {
     int32_t steps;    /* ascent steps, >= 0                                        */
     float eta0;       /* initial step length in normalised units (grid cells), >= 0 */
+    float grow;       /* step growth after an accepted step, >= 1 (e.g. 1.25)       */
     float scale[3];   /* unit of the normalised coordinates per component (A, B, q),
                          e.g. the coarse grid spacing                              */
     float lo[3];      /* the parameters stay inside [lo, hi] per component         */
@@ -176,8 +177,8 @@ typedef struct semb_refine_opts {
  * (A, B, q) (FP32 [n_out][3], read and overwritten; CMP keeps A = B = 0).  In
  * coordinates u = theta / scale each step moves u a distance eta along the
  * ascent direction dS/du / |dS/du| (dS/dtheta as in semblance_grad), clamps
- * to [lo, hi], and keeps the step only if S increases (eta then grows by
- * 1.25); otherwise eta halves.  Writes the final S and stack to s_out,
+ * to [lo, hi], and keeps the step only if S increases (eta then grows by the
+ * factor `grow`); otherwise eta halves.  Writes the final S and stack to s_out,
  * stack_out [n_out].  Rows are independent; the whole loop runs on the device
  * in one launch. */
 semb_status semb_refine(const semb_gathers *g, const semb_jobs *jobs, int32_t kind, float *theta,

@@ -54,7 +54,7 @@ class COutputs(C.Structure):
 
 
 class CRefineOpts(C.Structure):
-    _fields_ = [("steps", C.c_int32), ("eta0", C.c_float), ("scale", C.c_float * 3), ("lo", C.c_float * 3),
+    _fields_ = [("steps", C.c_int32), ("eta0", C.c_float), ("grow", C.c_float), ("scale", C.c_float * 3), ("lo", C.c_float * 3),
                 ("hi", C.c_float * 3)]
 
 
@@ -457,11 +457,11 @@ def theta_from_best(best, q, theta, A=None, B=None, stream=None):
 
 def refine(g: DeviceGathers, jobs: DeviceJobs, kind: int, theta, w: int, s_out, stack_out, steps: int = 8,
            eta0: float = 0.5, scale=(1.0, 1.0, 1.0), lo=(-1e30, -1e30, -1e30), hi=(1e30, 1e30, 1e30),
-           stream=None):
+           stream=None, grow: float = 1.25):
     """Gradient-ascent refinement of theta [n_out, 3] in place (see semb_refine)."""
     import torch
     gs, js = g.cstruct(), jobs.cstruct()
-    o = CRefineOpts(int(steps), float(eta0), (C.c_float * 3)(*scale), (C.c_float * 3)(*lo),
+    o = CRefineOpts(int(steps), float(eta0), float(grow), (C.c_float * 3)(*scale), (C.c_float * 3)(*lo),
                     (C.c_float * 3)(*hi))
     _check(lib().semb_refine(C.byref(gs), C.byref(js), int(kind), _typed(theta, torch.float32, "theta"),
                              C.byref(o), int(w), _typed(s_out, torch.float32, "s_out"),

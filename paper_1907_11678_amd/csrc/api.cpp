@@ -518,8 +518,8 @@ semb_status semb_refine(const semb_gathers *g, const semb_jobs *jobs, int32_t ki
     TRY(check_jobs(jobs, crs, g));
     TRY(check_w(w));
     if (!o) return fail(SEMB_EINVAL, "refine options are NULL");
-    if (o->steps < 0 || !(o->eta0 >= 0.f) || !isfinite(o->eta0))
-        return fail(SEMB_EINVAL, "steps must be >= 0 and eta0 finite and >= 0");
+    if (o->steps < 0 || !(o->eta0 >= 0.f) || !isfinite(o->eta0) || !(o->grow >= 1.f) || !isfinite(o->grow))
+        return fail(SEMB_EINVAL, "steps must be >= 0, eta0 finite and >= 0, grow finite and >= 1");
     for (int k = 0; k < 3; ++k)
         if (!isfinite(o->scale[k]) || !(o->lo[k] <= o->hi[k]))
             return fail(SEMB_EINVAL, "scale must be finite and lo <= hi for every component");
@@ -548,6 +548,7 @@ semb_status semb_refine(const semb_gathers *g, const semb_jobs *jobs, int32_t ki
     r.theta = theta;
     r.steps = o->steps;
     r.eta0 = o->eta0;
+    r.grow = o->grow;
     for (int k = 0; k < 3; ++k) {
         r.scale[k] = o->scale[k];
         r.lo[k] = o->lo[k];

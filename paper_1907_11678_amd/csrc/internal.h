@@ -108,6 +108,7 @@ struct RefineArgs {
     float *theta;  // [n_out][3], read and overwritten
     int32_t steps;
     float eta0;
+    float grow;
     float scale[3];
     float lo[3];
     float hi[3];

@@ -277,7 +277,7 @@ refine_kernel(PointArgs a, RefineArgs o)
             cur = nxt;
 #pragma unroll
             for (int k = 0; k < 3; ++k) th[k] = tr[k];
-            eta *= 1.25f;
+            eta *= o.grow;
         } else {
             eta *= 0.5f;
         }
