@@ -279,7 +279,7 @@ semb_status scan_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_
  * Tuned tile shapes are the counterpart of the paper's tuning of its tile and
  * prefetch sizes to the local store (section 3.3, Eq. (2)).
  * ------------------------------------------------------------------------- */
-#define SEMB_SCAN_SHAPES 4
+#define SEMB_SCAN_SHAPES 6
 
 /* Human-readable description of a shape, NULL if out of range. [host] */
 const char *semb_shape_name(int32_t shape);

@@ -349,7 +349,7 @@ def alloc_workspace(nsamples: int, device="cuda"):
 # ---------------------------------------------------------------------------
 # tile shapes of the exhaustive scan and their tuner
 # ---------------------------------------------------------------------------
-SCAN_SHAPES = 4
+SCAN_SHAPES = 6
 
 
 def shape_name(shape: int) -> str | None:

@@ -4,6 +4,7 @@
 
 #include <math.h>
 #include <stdarg.h>
+#include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -201,6 +202,8 @@ const char *const kShapeNames[semb::kScanShapes] = {
     "8 waves x 2 parameters, 3072-sample stage, branch-free windows",
     "8 waves x 2 parameters, 3072-sample stage, windows behind a branch",
     "4 waves x 4 parameters (2 for w > 15), 2048-sample stage, branch-free windows",
+    "8 waves x 4 parameters (2 for w > 15), 2048-sample stage, windows behind a branch",
+    "16 waves x 4 parameters (2 for w > 15), 2048-sample stage, windows behind a branch",
 };
 
 // shape < 0: the tuned (or default) shape for this call's key
@@ -670,7 +673,44 @@ semb_status semb_tune_scan(const semb_gathers *g, const semb_jobs *jobs, int32_t
     TRY(hip_status(hipStreamSynchronize(stream), "semb_tune_scan: synchronize"));
     size_t nrows = 0;
     for (int j = 0; j < sub.njobs; ++j) nrows += (size_t)std::max(0, nsv[cen[j]]);
+    // one copy per array when the sampled rows are (nearly) contiguous
+    int64_t rlo = INT64_MAX, rhi = 0;
+    for (int j = 0; j < sub.njobs; ++j) {
+        const int64_t n = std::max(0, nsv[cen[j]]);
+        if (n == 0) continue;
+        rlo = std::min(rlo, off[j]);
+        rhi = std::max(rhi, off[j] + n);
+    }
+    const bool span = rhi > rlo && (size_t)(rhi - rlo) <= 2 * nrows;
     auto fetch = [&](std::vector<int32_t> &b, std::vector<float> &sb, std::vector<float> &st) -> semb_status {
+        if (span) {
+            const size_t n = (size_t)(rhi - rlo);
+            b.resize(n);
+            sb.resize(n);
+            st.resize(n);
+            TRY(hip_status(hipMemcpyAsync(b.data(), out->best + rlo, 4 * n, hipMemcpyDeviceToHost, stream), "copy"));
+            TRY(hip_status(hipMemcpyAsync(sb.data(), out->s_best + rlo, 4 * n, hipMemcpyDeviceToHost, stream),
+                           "copy"));
+            TRY(hip_status(hipMemcpyAsync(st.data(), out->stack + rlo, 4 * n, hipMemcpyDeviceToHost, stream),
+                           "copy"));
+            TRY(hip_status(hipStreamSynchronize(stream), "semb_tune_scan: synchronize"));
+            // keep only the sampled rows (rows between jobs may hold anything)
+            std::vector<char> keep(n, 0);
+            for (int j = 0; j < sub.njobs; ++j)
+                for (int64_t r = off[j]; r < off[j] + std::max(0, nsv[cen[j]]); ++r) keep[(size_t)(r - rlo)] = 1;
+            size_t k = 0;
+            for (size_t i = 0; i < n; ++i)
+                if (keep[i]) {
+                    b[k] = b[i];
+                    sb[k] = sb[i];
+                    st[k] = st[i];
+                    ++k;
+                }
+            b.resize(k);
+            sb.resize(k);
+            st.resize(k);
+            return SEMB_OK;
+        }
         b.resize(nrows);
         sb.resize(nrows);
         st.resize(nrows);
@@ -717,8 +757,8 @@ semb_status semb_tune_scan(const semb_gathers *g, const semb_jobs *jobs, int32_t
             st = fetch(rb, rs, rt);
         } else {
             st = fetch(cb, cs, ct);
-            same = cb == rb && memcmp(cs.data(), rs.data(), 4 * nrows) == 0 &&
-                   memcmp(ct.data(), rt.data(), 4 * nrows) == 0;
+            same = cb == rb && cs.size() == rs.size() && memcmp(cs.data(), rs.data(), 4 * rs.size()) == 0 &&
+                   memcmp(ct.data(), rt.data(), 4 * rt.size()) == 0;
         }
         if (st != SEMB_OK) break;
         if (ms) ms[sid] = same ? t : -1.f;

@@ -120,7 +120,7 @@ hipError_t launch_window_energy(const float *samples, const int64_t *sample_off,
                                 int32_t ntraces, int32_t w, float *u0, float *u1, float *u2sq,
                                 hipStream_t stream);
 // Exhaustive scan in tile shape `shape` (0 .. kScanShapes - 1).
-constexpr int kScanShapes = 4;
+constexpr int kScanShapes = 6;
 hipError_t launch_scan(int kind, const ScanArgs &a, int shape, hipStream_t stream);
 hipError_t launch_scan_cmp(const ScanArgs &a, int shape, hipStream_t stream);
 hipError_t launch_scan_crs(const ScanArgs &a, int shape, hipStream_t stream);

@@ -519,7 +519,11 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
 //      favour occupancy);
 //   2: 8 waves x 2 parameters, 3072-position stage, windows behind a branch;
 //   3: 4 waves x 4 parameters (2 for w > 15), 2048-position stage,
-//      branch-free windows.
+//      branch-free windows;
+//   4: 8 waves x 4 parameters (2 for w > 15), 2048-position stage, windows
+//      behind a branch: twice the parameters per staged chunk;
+//   5: 16 waves x 4 parameters (2 for w > 15), 2048-position stage, windows
+//      behind a branch: four times the parameters per staged chunk.
 // ---------------------------------------------------------------------------
 template <int SID, int W>
 struct ShapeT;
@@ -542,6 +546,17 @@ template <int W>
 struct ShapeT<3, W> {
     static constexpr int NW = 4, P = W <= 15 ? 4 : 2, CAP = 2048, TMAX = 128, WPE = 4;
     static constexpr bool BRANCHY = false;
+};
+
+template <int W>
+struct ShapeT<4, W> {
+    static constexpr int NW = 8, P = W <= 15 ? 4 : 2, CAP = 2048, TMAX = 128, WPE = 2;
+    static constexpr bool BRANCHY = true;
+};
+template <int W>
+struct ShapeT<5, W> {
+    static constexpr int NW = 16, P = W <= 15 ? 4 : 2, CAP = 2048, TMAX = 128, WPE = 4;
+    static constexpr bool BRANCHY = true;
 };
 
 // The exhaustive scan: one workgroup per (job, sample block), all parameters.
@@ -612,6 +627,8 @@ hipError_t launch_scan_kind(const ScanArgs &a, int sid, hipStream_t stream)
     case 1: return launch_s<KIND, 1>(a, stream);
     case 2: return launch_s<KIND, 2>(a, stream);
     case 3: return launch_s<KIND, 3>(a, stream);
+    case 4: return launch_s<KIND, 4>(a, stream);
+    case 5: return launch_s<KIND, 5>(a, stream);
     default: return hipErrorInvalidValue;
     }
 }

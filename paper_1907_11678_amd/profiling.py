@@ -5,6 +5,10 @@ record of a kernel.
         Markdown table of a `rocprofv3 --kernel-trace --stats
         --output-format csv` run (per kernel: calls, total, average, share).
 
+    python -m paper_1907_11678_amd.profiling trace <kernel_trace.csv>
+        The same per (kernel, grid size), so that full launches and a
+        tuner's sample launches of one kernel are told apart.
+
     python -m paper_1907_11678_amd.profiling traffic <fetch_csv> <write_csv>
             <kernel-substring> <copy-bytes> <out.txt>
         Reduce two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs
@@ -53,33 +57,53 @@ def kernel_stats_table(path: str, top: int = 12) -> str:
 
 
 def _per_dispatch(path: str, counter: str):
-    """{kernel name: [value per dispatch]} for one counter (summed over the
-    dimensions rocprofv3 may report separately)."""
+    """{kernel name: [(grid size, value) per dispatch]} for one counter (summed
+    over the dimensions rocprofv3 may report separately)."""
     acc = defaultdict(float)
-    names = {}
+    meta = {}
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
         d = int(r["Dispatch_Id"])
         acc[d] += float(r["Counter_Value"])
-        names[d] = r["Kernel_Name"]
+        meta[d] = (r["Kernel_Name"], int(r["Grid_Size"]))
     by = defaultdict(list)
     for d in sorted(acc):
-        by[names[d]].append(acc[d])
+        by[meta[d][0]].append((meta[d][1], acc[d]))
     return by
 
 
 def _mean_of(by, sub: str, largest: bool = False):
-    """Mean counter value over the dispatches of the kernel matching `sub`;
-    with largest=True only over the dispatches within 2x of the largest (the
-    calibration copies, not the small uploads that use the same kernel)."""
-    vals = [v for k, vs in by.items() if sub in k for v in vs]
-    if not vals:
+    """Mean counter value over the largest-grid dispatches of the kernel
+    matching `sub` (the full launches, not a tuner's sample runs); with
+    largest=True over the dispatches whose value is within 2x of the largest
+    (the calibration copies, not the small uploads that use the same kernel)."""
+    items = [gv for k, gvs in by.items() if sub in k for gv in gvs]
+    if not items:
         raise SystemExit(f"no dispatch of a kernel matching {sub!r}")
     if largest:
-        top = max(vals)
-        vals = [v for v in vals if v >= 0.5 * top]
+        top = max(v for _, v in items)
+        vals = [v for _, v in items if v >= 0.5 * top]
+    else:
+        gmax = max(g for g, _ in items)
+        vals = [v for g, v in items if g == gmax]
     return sum(vals) / len(vals), len(vals), [k for k in by if sub in k][0]
+
+
+def kernel_trace_table(path: str, top: int = 12) -> str:
+    """Per (kernel, grid size) from a kernel_trace.csv: launches and mean /
+    min / max duration, largest total first."""
+    acc = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        ns = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        grid = int(r.get("Grid_Size_X", r.get("Grid_Size", 0)) or 0)
+        acc[(r["Kernel_Name"], grid)].append(ns)
+    rows = sorted(acc.items(), key=lambda kv: -sum(kv[1]))[:top]
+    out = ["| kernel | grid (work-items) | launches | mean ms | min ms | max ms |", "|---|---|---|---|---|---|"]
+    for (name, grid), v in rows:
+        out.append(f"| `{name}` | {grid} | {len(v)} | {sum(v) / len(v) / 1e6:.3f} | {min(v) / 1e6:.3f} | "
+                   f"{max(v) / 1e6:.3f} |")
+    return "\n".join(out)
 
 
 def traffic_record(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int) -> dict:
@@ -132,6 +156,8 @@ def current_traffic(path: str) -> float | None:
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         print(kernel_stats_table(argv[1]))
+    elif len(argv) >= 2 and argv[0] == "trace":
+        print(kernel_trace_table(argv[1]))
     elif len(argv) == 6 and argv[0] == "traffic":
         rec = traffic_record(argv[1], argv[2], argv[3], int(argv[4]))
         write_record(rec, argv[5])

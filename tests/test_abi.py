@@ -191,7 +191,7 @@ def test_shape_names_and_host_side_table(semb):
     g2 = _gathers(semb, ntraces=600, ngathers=20, ns_max=1900)  # another ns bucket
     assert L.semb_scan_shape(1, 11, C.byref(g2), C.byref(j)) == 1
     assert L.semb_scan_shape(1, 9, C.byref(g), C.byref(j)) == 1   # other window
-    assert L.semb_set_scan_shape(1, 11, C.byref(g), C.byref(j), 4) == 1
+    assert L.semb_set_scan_shape(1, 11, C.byref(g), C.byref(j), semb.SCAN_SHAPES) == 1
     assert L.semb_set_scan_shape(2, 11, C.byref(g), C.byref(j), 0) == 1
     assert L.semb_set_scan_shape(1, 11, C.byref(g), C.byref(j), -1) == 0
     assert L.semb_scan_shape(1, 11, C.byref(g), C.byref(j)) == 1
@@ -209,3 +209,8 @@ def test_tuner_rejects_bad_arguments(semb):
                             C.c_void_p(0x10000), 1 << 20, None, None, None) == 1
     assert L.semb_tune_scan(C.byref(g), C.byref(j), 5, None, 1, None, 1, P, 8, 11, 4, 1, C.byref(out),
                             C.c_void_p(0x10000), 1 << 20, C.byref(shape), None, None) == 1
+
+
+def test_shape_count_matches_the_header(semb):
+    text = open(HEADER).read()
+    assert f"#define SEMB_SCAN_SHAPES {semb.SCAN_SHAPES}" in text
