@@ -311,7 +311,8 @@ def crs_leg(torch, synth, semb, dev, stream):
     st = torch.empty(n, dtype=torch.float32, device=dev)
     ws = semb.alloc_workspace(dg.nsamples)
     A, B, q = (torch.from_numpy(x).to(dev) for x in (wl.grid.A, wl.grid.B, wl.grid.q))
-    shape, _ = semb.tune_scan(1, dg, dj, q, wl.w, best, sb, st, ws, A=A, B=B, sample_jobs=32, reps=1,
+    # 128 centrals x 16 sample blocks: four rounds of workgroups on 256 CUs
+    shape, _ = semb.tune_scan(1, dg, dj, q, wl.w, best, sb, st, ws, A=A, B=B, sample_jobs=128, reps=1,
                               stream=stream)
     semb.crs_scan(dg, dj, A, B, q, wl.w, best, sb, st, ws, stream=stream)
     torch.cuda.synchronize()
@@ -360,7 +361,7 @@ def refine_leg(torch, synth, semb, dev, stream, fine):
     hi = (float(coarse.A.max()), float(coarse.B.max()), float(coarse.q.max()))
 
     s = torch.cuda.Stream()
-    shape, _ = semb.tune_scan(1, dg, dj, q, wl.w, best, s0, st0, ws, A=A, B=B, sample_jobs=64, reps=1, stream=s)
+    shape, _ = semb.tune_scan(1, dg, dj, q, wl.w, best, s0, st0, ws, A=A, B=B, sample_jobs=128, reps=2, stream=s)
 
     def run():
         semb.crs_scan(dg, dj, A, B, q, wl.w, best, s0, st0, ws, stream=s)

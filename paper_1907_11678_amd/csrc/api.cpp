@@ -762,7 +762,8 @@ semb_status semb_tune_scan(const semb_gathers *g, const semb_jobs *jobs, int32_t
         }
         if (st != SEMB_OK) break;
         if (ms) ms[sid] = same ? t : -1.f;
-        if (same && (k == 0 || t < best_ms)) {
+        // another shape must beat the default by 2% (timing noise does not flip the choice)
+        if (same && (k == 0 || t < (best_shape == d ? 0.98f : 1.f) * best_ms)) {
             best_ms = t;
             best_shape = sid;
         }
