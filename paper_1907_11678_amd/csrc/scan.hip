@@ -14,14 +14,23 @@ namespace {
 // energy sum_j (a_j + x b_j)^2 = aa + 2 x ab + x^2 bb equals
 //   (u0 + u1 x)^2 + u2sq,  u1 = sqrt(bb), u0 = ab / u1, u2sq = aa - ab^2 / bb
 // (u1 = u0 = 0, u2sq = aa when bb = 0).  The sums are formed in FP64, where
-// products of FP32 samples are exact.  One block per trace.
+// products of FP32 samples are exact; 1/sqrt(bb) comes from the hardware
+// reciprocal square root plus one Newton step (relative error ~1e-15), so
+// u0, u1 and u2sq are the FP32 roundings of their exact values up to a few
+// units in the last place of FP64.  One block per trace: the trace is staged
+// in LDS 2048 positions at a time (coalesced loads), each thread then forms
+// the sums of its positions from LDS, and the three planes are written
+// coalesced.
 // ---------------------------------------------------------------------------
+constexpr int ENERGY_PIECE = 2048;
+
+template <int W>
 __global__ void __launch_bounds__(256)
 window_energy_kernel(const float *__restrict__ samples, const int64_t *__restrict__ sample_off,
                      const int32_t *__restrict__ trace_ptr, const int32_t *__restrict__ ns,
-                     int ngathers, int w, float *__restrict__ u0, float *__restrict__ u1,
-                     float *__restrict__ u2sq)
+                     int ngathers, float *__restrict__ u0, float *__restrict__ u1, float *__restrict__ u2sq)
 {
+    __shared__ float sf[ENERGY_PIECE + 32];
     const int t = blockIdx.x;
     int lo = 0, hi = ngathers;  // largest g with trace_ptr[g] <= t
     while (hi - lo > 1) {
@@ -30,33 +39,53 @@ window_energy_kernel(const float *__restrict__ samples, const int64_t *__restric
     }
     const int n = ns[lo];
     const int64_t base = sample_off[lo] + (int64_t)(t - trace_ptr[lo]) * n;
-    for (int p = threadIdx.x; p < n; p += blockDim.x) {
-        float r0 = 0.f, r1 = 0.f, r2 = 0.f;
-        if (p + w <= n - 1) {
-            const float *f = samples + base + p;
-            double aa = 0.0, ab = 0.0, bb = 0.0;
-            double prev = f[0];
-            for (int j = 0; j < w; ++j) {
-                const double nxt = f[j + 1];
-                const double d = nxt - prev;  // exact: both are FP32 values
-                aa = fma(prev, prev, aa);
-                ab = fma(prev, d, ab);
-                bb = fma(d, d, bb);
-                prev = nxt;
+    for (int p0 = 0; p0 < n; p0 += ENERGY_PIECE) {
+        const int nload = min(n - p0, ENERGY_PIECE + W + 1);  // <= ENERGY_PIECE + 32
+        __syncthreads();  // the previous piece is done with sf
+        for (int i = threadIdx.x; i < nload; i += blockDim.x) sf[i] = samples[base + p0 + i];
+        __syncthreads();
+        const int pend = min(n, p0 + ENERGY_PIECE);
+        for (int p = p0 + (int)threadIdx.x; p < pend; p += blockDim.x) {
+            float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+            if (p + W <= n - 1) {  // then all W + 1 samples are staged
+                const float *f = sf + (p - p0);
+                double aa = 0.0, ab = 0.0, bb = 0.0;
+                double prev = f[0];
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    const double nxt = f[j + 1];
+                    const double d = nxt - prev;  // exact: both are FP32 values
+                    aa = fma(prev, prev, aa);
+                    ab = fma(prev, d, ab);
+                    bb = fma(d, d, bb);
+                    prev = nxt;
+                }
+                if (bb > 0.0) {
+                    double y = __builtin_amdgcn_rsq(bb);
+                    y = fma(fma(-bb * y, y, 1.0), 0.5 * y, y);  // one Newton step
+                    const double c0 = ab * y;
+                    r1 = (float)(bb * y);
+                    r0 = (float)c0;
+                    r2 = (float)fmax(fma(-c0, c0, aa), 0.0);
+                } else {
+                    r2 = (float)aa;
+                }
             }
-            if (bb > 0.0) {
-                const double s1 = sqrt(bb);
-                r1 = (float)s1;
-                r0 = (float)(ab / s1);
-                r2 = (float)fmax(aa - ab * ab / bb, 0.0);
-            } else {
-                r2 = (float)aa;
-            }
+            u0[base + p] = r0;
+            u1[base + p] = r1;
+            u2sq[base + p] = r2;
         }
-        u0[base + p] = r0;
-        u1[base + p] = r1;
-        u2sq[base + p] = r2;
     }
+}
+
+template <int W>
+hipError_t launch_energy_w(const float *samples, const int64_t *sample_off, const int32_t *trace_ptr,
+                           const int32_t *ns, int32_t ngathers, int32_t ntraces, float *u0, float *u1,
+                           float *u2sq, hipStream_t stream)
+{
+    hipLaunchKernelGGL((window_energy_kernel<W>), dim3((unsigned)ntraces), dim3(256), 0, stream, samples,
+                       sample_off, trace_ptr, ns, ngathers, u0, u1, u2sq);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -190,9 +219,15 @@ hipError_t launch_window_energy(const float *samples, const int64_t *sample_off,
                                 hipStream_t stream)
 {
     if (ntraces <= 0) return hipSuccess;
-    hipLaunchKernelGGL(window_energy_kernel, dim3((unsigned)ntraces), dim3(256), 0, stream, samples,
-                       sample_off, trace_ptr, ns, ngathers, w, u0, u1, u2sq);
-    return hipGetLastError();
+#define SEMB_ENERGY(WW) \
+    case WW: return launch_energy_w<WW>(samples, sample_off, trace_ptr, ns, ngathers, ntraces, u0, u1, u2sq, stream);
+    switch (w) {
+        SEMB_ENERGY(1) SEMB_ENERGY(3) SEMB_ENERGY(5) SEMB_ENERGY(7) SEMB_ENERGY(9) SEMB_ENERGY(11)
+        SEMB_ENERGY(13) SEMB_ENERGY(15) SEMB_ENERGY(17) SEMB_ENERGY(19) SEMB_ENERGY(21) SEMB_ENERGY(23)
+        SEMB_ENERGY(25) SEMB_ENERGY(27) SEMB_ENERGY(29) SEMB_ENERGY(31)
+    default: return hipErrorInvalidValue;
+    }
+#undef SEMB_ENERGY
 }
 
 hipError_t launch_scan(int kind, const ScanArgs &a, int shape, hipStream_t stream)

@@ -31,8 +31,7 @@ from collections import defaultdict
 PKG = os.path.dirname(os.path.abspath(__file__))
 # sources whose change (with the compiler flags) invalidates a traffic record
 # of the scan kernels
-KERNEL_SOURCES = ("csrc/tile.h", "csrc/scan.hip", "csrc/scan_cmp.hip", "csrc/scan_crs.hip", "csrc/internal.h",
-                  "csrc/traveltime.h")
+KERNEL_SOURCES = ("csrc/tile.h", "csrc/scan_cmp.hip", "csrc/scan_crs.hip", "csrc/internal.h", "csrc/traveltime.h")
 COPY_KERNEL = "copyBuffer"
 
 
