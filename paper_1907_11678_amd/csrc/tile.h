@@ -368,9 +368,9 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                 __syncthreads();
 
                 // ---- the hot loop: traces outer, this lane's P parameters inner ----
-                // The valid set is decided on T > 0: T = 0 only arises from
-                // s = 0 with nothing else (handled by s2e above) or exactly on
-                // a CRS surface's edge, a set of measure zero.
+                // A trace counts iff T > 0 and its window lies on the trace; T = 0
+                // only arises from s = 0 with nothing else (handled by s2e above)
+                // or exactly on a CRS surface's edge, a set of measure zero.
                 double qd[P];  // this wave's parameters (CMP), held in scalar registers
 #pragma unroll
                 for (int p = 0; p < P; ++p) qd[p] = to_sgpr(L.pq[wv * P + p]);
@@ -390,11 +390,13 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                                 } else {
                                     T = fma(qd[p], cc, s2e);
                                 }
-                                // tau < 2^30 keeps the conversion exact (floor); NaN
-                                // from T <= 0 becomes 2^30, rejected with T below
+                                // tau < 2^30 keeps the conversion exact (floor); the
+                                // NaN that T <= 0 gives (and +inf's) becomes 2^30, a
+                                // window start no trace has: the range test below
+                                // rejects those traces without a test on T
                                 const double tau = fmin(sqrt_newton(T), 1073741824.0);
                                 const int a = (int)tau - HW;
-                                if (!((unsigned)a <= (unsigned)lim && T > 0.0)) continue;
+                                if (!((unsigned)a <= (unsigned)lim)) continue;
                                 const float x = (float)__builtin_amdgcn_fract(tau);
                                 const float u = 1.f - x;
                                 const int id = a + off;
@@ -424,7 +426,7 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                                 }
                                 const double tau = fmin(sqrt_newton(T), 1073741824.0);
                                 const int a = (int)tau - HW;
-                                const bool ok = (unsigned)a <= (unsigned)lim && T > 0.0;
+                                const bool ok = (unsigned)a <= (unsigned)lim;
                                 idx[p] = ok ? a + off : 0;
                                 xw[p] = ok ? (float)__builtin_amdgcn_fract(tau) : 0.f;
                                 vm[p] = ok ? 1.f : 0.f;
