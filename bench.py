@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--cmp-only", action="store_true", help="skip the CRS, batched and refinement legs")
     ap.add_argument("--gathers", type=int, default=20000, help="(testing only) fewer CMP gathers")
     ap.add_argument("--cpu-gathers", type=int, default=384, help="CMP gathers in the CPU oracle sample")
+    ap.add_argument("--paper-shapes", action="store_true",
+                    help="also measure the paper's Table 1 dataset shapes (CMP and CRS)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (counter calibration)")
     args = ap.parse_args()
@@ -253,6 +255,10 @@ def main():
         del fine
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(torch, synth, semb, dev, stream)
+
+    if args.paper_shapes:
+        out["paper_shapes"] = paper_shapes_leg(torch, synth, semb, dev, stream)
+        torch.cuda.empty_cache()
 
     # ---- CPU oracle baseline ---------------------------------------------
     if not args.no_cpu:
@@ -443,6 +449,80 @@ def batched_leg(torch, synth, semb, dev, stream):
                         "launch in a HIP graph",
             "value": ev / (t_ms * 1e-3), "unit": "evals/s", "graph_ms": t_ms, "kernel_ms_eager": kt.ms[0],
             "evals": ev, "evals_cmp": ev_c, "evals_crs": ev_r, "tiles": int(tiles.shape[0])}
+
+
+def _scan_rate(torch, semb, wl, dev, stream, tune_jobs):
+    """Tuned shape, then 3 timed calls of the scan over workload wl: evals/s and
+    the scan kernel's mean time."""
+    import synth
+    gs, jobs = wl.gathers, wl.jobs
+    crs = wl.kind == "crs"
+    dg = semb.upload_gathers(gs.samples, gs.sample_off, gs.trace_ptr, gs.ns, gs.half_offset, gs.midpoint,
+                             gs.central_x, gs.dt, device=dev)
+    dj = semb.upload_jobs(jobs.central, jobs.apert_ptr if crs else None, jobs.apert_gather if crs else None,
+                          jobs.out_off, jobs.n_out, device=dev)
+    n = jobs.n_out
+    best = torch.empty(n, dtype=torch.int32, device=dev)
+    sb = torch.empty(n, dtype=torch.float32, device=dev)
+    st = torch.empty(n, dtype=torch.float32, device=dev)
+    ws = semb.alloc_workspace(dg.nsamples)
+    q = torch.from_numpy(wl.grid.q).to(dev)
+    A = torch.from_numpy(wl.grid.A).to(dev) if crs else None
+    B = torch.from_numpy(wl.grid.B).to(dev) if crs else None
+    shape, _ = semb.tune_scan(1 if crs else 0, dg, dj, q, wl.w, best, sb, st, ws, A=A, B=B,
+                              sample_jobs=tune_jobs, reps=1, stream=stream)
+
+    def call():
+        if crs:
+            semb.crs_scan(dg, dj, A, B, q, wl.w, best, sb, st, ws, stream=stream)
+        else:
+            semb.cmp_scan(dg, dj, q, wl.w, best, sb, st, ws, stream=stream)
+
+    call()
+    torch.cuda.synchronize()
+    with semb.KernelTimer(3) as kt:
+        t0 = time.perf_counter()
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / 3
+    evals = synth.count_evals(gs, jobs, wl.grid)
+    return {"evals": evals, "value": evals / wall, "ms_per_call": wall * 1e3,
+            "kernel_ms": sum(kt.ms) / len(kt.ms), "tile_shape": shape}
+
+
+def paper_shapes_leg(torch, synth, semb, dev, stream):
+    """The eight dataset shapes of the paper's Table 1 (fold 60 / 1000, 550 /
+    1650 samples; the "dt" column read as the window, 19 or 17 samples):
+    CMP over a line of gathers (101 velocities) and CRS over +-2 gathers with
+    the coarse 7 x 7 x 11 grid.  The numbers of gathers are chosen to keep each
+    call in the tens to hundreds of milliseconds (the paper's datasets hold
+    61,628 to 2,648,430 CDPs)."""
+    cmp_gathers = {(60, 550): 3000, (60, 1650): 1200, (1000, 550): 360, (1000, 1650): 240}
+    crs_centrals = {(60, 550): 256, (60, 1650): 128, (1000, 550): 128, (1000, 1650): 64}
+    import dataclasses
+    res = {}
+    k = 2
+    for d0 in (1, 3, 5, 7):  # datasets d0 and d0 + 1 share fold, ns and data
+        fold, ns, _ = synth.PAPER_DATASETS[d0]
+        t = time.time()
+        wl0 = synth.paper_shape(d0, cmp_gathers[(fold, ns)])
+        nc = crs_centrals[(fold, ns)]
+        wc0 = synth.paper_shape(d0, nc + 2 * k, kind="crs", half_aperture=k)
+        log(f"generated the fold {fold} x {ns} lines in {time.time() - t:.1f} s")
+        for d in (d0, d0 + 1):
+            w = synth.paper_window(synth.PAPER_DATASETS[d][2])
+            wl = dataclasses.replace(wl0, w=w)
+            wc = dataclasses.replace(wc0, w=w)
+            r = _scan_rate(torch, semb, wl, dev, stream, tune_jobs=256)
+            rc = _scan_rate(torch, semb, wc, dev, stream, tune_jobs=max(16, nc // 2))
+            res[f"data{d}"] = {"fold": fold, "samples": ns, "window": w, "cmp_gathers": wl.jobs.njobs,
+                               "cmp": r, "crs_centrals": wc.jobs.njobs, "crs": rc}
+            log(f"paper data{d} (fold {fold}, ns {ns}, w {w}): CMP {r['value']:.3e} evals/s, "
+                f"CRS {rc['value']:.3e} evals/s")
+        del wl0, wc0, wl, wc
+        torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

@@ -288,8 +288,9 @@ const char *semb_shape_name(int32_t shape);
  * and `reps` timed calls each), compares each shape's best / s_best / stack
  * rows of those jobs with the default shape's, and records the fastest shape
  * whose rows are bit-identical for this call's key (another shape must beat
- * the default by 2%; the sample should hold enough tiles -- jobs times
- * ceil(ns / 64) -- to fill the GPU several times, or tail effects decide); *shape receives it,
+ * the default by 2%).  The sample is raised to at least 8 tiles (jobs times
+ * ceil(ns_max / 64)) per compute unit when the workload has them: a sample
+ * that does not fill the GPU several times is decided by tail effects; *shape receives it,
  * ms[SEMB_SCAN_SHAPES] (nullable, host) each shape's mean time per call in
  * milliseconds, or -1 for a shape whose outputs differed.  Arguments as for
  * cmp_scan (kind CMP; A, B ignored) or crs_scan; the sampled jobs' output

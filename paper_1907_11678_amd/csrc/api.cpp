@@ -653,8 +653,14 @@ semb_status semb_tune_scan(const semb_gathers *g, const semb_jobs *jobs, int32_t
     const bool crs = kind == SEMB_KIND_CRS;
     TRY(check_gathers(g, crs));
     TRY(check_jobs(jobs, crs, g));
+    // at least four rounds of workgroups at two per CU, or tail effects decide
+    int dev = 0, cus = 0;
+    TRY(hip_status(hipGetDevice(&dev), "hipGetDevice"));
+    TRY(hip_status(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute"));
+    const int n_sblk = std::max(1, (g->ns_max + 63) / 64);
+    const long long min_jobs = (8LL * std::max(cus, 1) + n_sblk - 1) / n_sblk;
     semb_jobs sub = *jobs;
-    sub.njobs = std::min(sample_jobs, jobs->njobs);
+    sub.njobs = (int32_t)std::min<long long>(std::max<long long>(sample_jobs, min_jobs), jobs->njobs);
     for (int s = 0; s < semb::kScanShapes && ms; ++s) ms[s] = -1.f;
     *shape = chosen_shape(kind, w, g, jobs);
     if (sub.njobs == 0) return SEMB_OK;

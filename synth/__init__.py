@@ -541,3 +541,67 @@ def batched_line(ids=None, half_aperture: int = 2) -> BatchWorkload:
                          grid_crs=Grid(A=uniform_grid(-5e-4, 5e-4, 11), B=uniform_grid(-1e-7, 1e-7, 11),
                                        q=velocity_grid(1500.0, 4500.0, 21)),
                          w_cmp=11, w_crs=9)
+
+
+# --------------------------------------------------------------------------
+# the paper's dataset shapes (Table 1): fold, samples per trace, and the
+# "dt" column, which sets how many samples one window access reads
+# --------------------------------------------------------------------------
+PAPER_DATASETS = {1: (60, 550, 220), 2: (60, 550, 240), 3: (60, 1650, 220), 4: (60, 1650, 240),
+                  5: (1000, 550, 220), 6: (1000, 550, 240), 7: (1000, 1650, 220), 8: (1000, 1650, 240)}
+
+
+def paper_window(dt_column: int) -> int:
+    """Window length read from Table 1's "dt" column taken as microseconds per
+    sample under a fixed +-2 ms window: 2 * floor(2000 / dt) + 1 samples (19 for
+    220, 17 for 240; the 19-sample window is 76 B of FP32, the largest access
+    the paper quotes)."""
+    return 2 * (2000 // int(dt_column)) + 1
+
+
+def paper_shape_spec(dataset: int, ngathers: int) -> LineSpec:
+    """A line of ``ngathers`` gathers with dataset ``dataset``'s fold and trace
+    length, sampled at 4 ms (the sampling interval itself is not given), the CRS
+    line's event model scaled to the line and to the trace length, SNR 3.  The
+    datasets that differ only in the "dt" column share their data."""
+    fold, ns, _ = PAPER_DATASETS[dataset]
+    t_end = 0.9 * ns * 0.004
+    return LineSpec(ngathers=ngathers, fold=fold, ns=ns, dt=0.004, h_max=1500.0,
+                    nevents=max(1, int(math.ceil(0.58 * ngathers))), f_peak=25.0, t0_range=(0.2, t_end),
+                    A_range=(-4e-4, 4e-4), B_range=(-8e-8, 8e-8), v_range=(1800.0, 4000.0),
+                    amp_range=(0.5, 1.0), taper_halfwidth=100.0, snr=3.0,
+                    seed=ROOT_SEED + 10 + (dataset - 1) // 2)  # datasets 2k-1 and 2k share fold and ns
+
+
+def paper_shape(dataset: int, ngathers: int, kind: str = "cmp", half_aperture: int = 2,
+                centrals=None) -> Workload:
+    """Dataset ``dataset`` of Table 1 at a chosen number of gathers.  CMP: one
+    job per gather, 101 velocities 1500..4500 m/s.  CRS: centrals (default: all
+    with a full aperture) with +-``half_aperture`` gathers and the coarse
+    7 x 7 x 11 grid.  The window follows ``paper_window``."""
+    fold, ns, dtc = PAPER_DATASETS[dataset]
+    spec = paper_shape_spec(dataset, ngathers)
+    w = paper_window(dtc)
+    if kind == "cmp":
+        ids = list(range(ngathers)) if centrals is None else list(centrals)
+        gs = line_gathers(spec, ids)
+        return Workload(name=f"paper_data{dataset}", kind="cmp", gathers=gs, jobs=cmp_jobs(gs),
+                        grid=Grid(q=velocity_grid(1500.0, 4500.0, 101)), w=w)
+    k = half_aperture
+    centrals = list(range(k, ngathers - k)) if centrals is None else list(centrals)
+    need = sorted({g for c in centrals for g in range(max(0, c - k), min(ngathers, c + k + 1))})
+    gs = line_gathers(spec, need)
+    pos = {g: i for i, g in enumerate(need)}
+    ptr, ag = [0], []
+    for c in centrals:
+        ag.extend(pos[g] for g in range(max(0, c - k), min(ngathers, c + k + 1)))
+        ptr.append(len(ag))
+    cen = np.array([pos[c] for c in centrals], np.int32)
+    nsv = gs.ns[cen].astype(np.int64)
+    out_off = np.zeros(cen.size, np.int64)
+    if cen.size > 1:
+        out_off[1:] = np.cumsum(nsv)[:-1]
+    jobs = Jobs(central=cen, apert_ptr=np.asarray(ptr, np.int32), apert_gather=np.asarray(ag, np.int32),
+                out_off=out_off, n_out=int(nsv.sum()))
+    return Workload(name=f"paper_data{dataset}_crs", kind="crs", gathers=gs, jobs=jobs,
+                    grid=crs_coarse_grid(), w=w)

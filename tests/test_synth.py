@@ -70,3 +70,18 @@ def test_noise_level_follows_snr():
     rms = np.sqrt(np.mean(clean.astype(np.float64) ** 2))
     noise = noisy.astype(np.float64) - clean
     assert abs(np.sqrt(np.mean(noise ** 2)) / rms - 1.0 / spec2.snr) < 0.01
+
+
+def test_paper_shapes():
+    assert synth.paper_window(220) == 19 and synth.paper_window(240) == 17
+    for d, (fold, ns, _) in synth.PAPER_DATASETS.items():
+        spec = synth.paper_shape_spec(d, 10)
+        assert spec.fold == fold and spec.ns == ns
+    wl = synth.paper_shape(5, 3)
+    assert wl.gathers.ngathers == 3 and int(wl.gathers.trace_ptr[-1]) == 3000
+    assert (wl.gathers.ns == 550).all() and wl.w == 19 and wl.grid.q.size == 101
+    sub = synth.paper_shape(5, 3, centrals=[2])
+    assert np.array_equal(sub.gathers.gather(0), wl.gathers.gather(2))
+    crs = synth.paper_shape(2, 9, kind="crs", half_aperture=1, centrals=[4])
+    assert crs.jobs.njobs == 1 and crs.gathers.ngathers == 3 and crs.w == 17
+    assert crs.grid.n == 7 * 7 * 11
