@@ -311,6 +311,21 @@ int32_t semb_scan_shape(int32_t kind, int32_t w, const semb_gathers *g, const se
 /* Forget every recorded shape. [host] */
 void semb_clear_tuning(void);
 
+/* CRS apertures by radius: for every central gather, the gathers whose
+ * midpoint (x, y) lies within `radius` of the central's (the paper's
+ * neighbourhood of a central CDP, section 2.2, Fig. 2b), central included, in
+ * increasing gather index.  x, y: [ngathers] midpoint coordinates in m (y may
+ * be NULL for a line); centrals: [ncentrals]; all host memory.  Fills
+ * apert_ptr[ncentrals + 1] and, when apert_gather is non-NULL, apert_gather
+ * [apert_ptr[ncentrals]] (call once with NULL to size it); *max_apert
+ * (nullable) receives the longest list, which crs_scan accepts up to
+ * SEMB_APERT_LIMIT.  Returns the number of entries, -1 on invalid input
+ * (semb_last_error).  A uniform grid hash with cells of the radius's size
+ * keeps each query to 3 x 3 cells.  [host] */
+int64_t semb_radius_apertures(const double *x, const double *y, int32_t ngathers, const int32_t *centrals,
+                              int32_t ncentrals, double radius, int32_t *apert_ptr, int32_t *apert_gather,
+                              int32_t *max_apert);
+
 /* Kernel timing for measurement.  After semb_kernel_timer_start(capacity),
  * the next `capacity` launches of a call's main kernel made by this thread
  * (the scan kernel of cmp_scan / crs_scan, the persistent kernel of

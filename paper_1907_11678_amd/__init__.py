@@ -116,6 +116,8 @@ def lib():
         L.semb_scan_shape.restype = i32
         L.semb_clear_tuning.argtypes = []
         L.semb_clear_tuning.restype = None
+        L.semb_radius_apertures.argtypes = [P, P, i32, P, i32, C.c_double, P, P, P]
+        L.semb_radius_apertures.restype = i64
         L.semb_kernel_timer_start.argtypes = [i32]
         L.semb_kernel_timer_start.restype = C.c_int
         L.semb_kernel_timer_stop.argtypes = [P, P, i32]
@@ -344,6 +346,31 @@ def alloc_workspace(nsamples: int, device="cuda"):
     ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
     off = (-ws.data_ptr()) % 256
     return ws[off:off + nbytes]
+
+
+# ---------------------------------------------------------------------------
+# CRS apertures by radius (host)
+# ---------------------------------------------------------------------------
+def radius_apertures(x, centrals, radius: float, y=None):
+    """(apert_ptr, apert_gather, max_apert) of the gathers within `radius` of
+    each central's midpoint (x[, y] per gather, metres)."""
+    import numpy as np
+    x = np.ascontiguousarray(x, np.float64)
+    yv = None if y is None else np.ascontiguousarray(y, np.float64)
+    cen = np.ascontiguousarray(centrals, np.int32)
+    ptr = np.zeros(cen.size + 1, np.int32)
+    mx = C.c_int32(0)
+    L = lib()
+    args = (x.ctypes.data, None if yv is None else yv.ctypes.data, int(x.size), cen.ctypes.data, int(cen.size),
+            float(radius))
+    n = L.semb_radius_apertures(*args, ptr.ctypes.data, None, C.byref(mx))
+    if n < 0:
+        raise SembError(1, last_error())
+    ag = np.zeros(max(int(n), 1), np.int32)
+    n2 = L.semb_radius_apertures(*args, ptr.ctypes.data, ag.ctypes.data, C.byref(mx))
+    if n2 != n:
+        raise SembError(1, last_error())
+    return ptr, ag[:n], int(mx.value)
 
 
 # ---------------------------------------------------------------------------

@@ -322,6 +322,8 @@ BatchLayout batch_layout(int64_t nsamples, int32_t w_cmp, int32_t w_crs, int32_t
 
 }  // namespace
 
+void semb::set_last_error(const char *msg) { g_last_error = msg; }
+
 extern "C" {
 
 int64_t semb_batch_plan(const semb_batch_host *h, int32_t split_params, semb_tile *tiles, int64_t max_tiles,

@@ -114,6 +114,9 @@ struct RefineArgs {
     float hi[3];
 };
 
+// Records the message semb_last_error() returns on this thread.
+void set_last_error(const char *msg);
+
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_window_energy(const float *samples, const int64_t *sample_off,
                                 const int32_t *trace_ptr, const int32_t *ns, int32_t ngathers,
