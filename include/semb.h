@@ -193,6 +193,23 @@ semb_status semb_theta_from_best(const int32_t *best, int64_t n_out, const float
                                  const float *B, int32_t nB, const float *q, int32_t nq, float *theta,
                                  hipStream_t stream);
 
+/* Starting points for a multi-start refinement: for each of n_rows rows of a
+ * semblance panel (FP32 [n_rows][nA * nB * nq], as a scan writes it), the K
+ * (1 .. 8) largest local maxima over the nA x nB x nq grid, best first (flat
+ * index (iA * nB + iB) * nq + iq).  A cell is a local maximum when each of
+ * its up to 26 neighbours is smaller, or equal with a larger flat index.  A
+ * row with fewer than K maxima repeats its best.  best_k [K][n_rows] (int32)
+ * and s_k [K][n_rows] (FP32), start-major, so that column k feeds
+ * semb_theta_from_best directly. */
+semb_status semb_panel_peaks(const float *panel, int64_t n_rows, int32_t nA, int32_t nB, int32_t nq, int32_t K,
+                             int32_t *best_k, float *s_k, hipStream_t stream);
+
+/* The best of K refined candidates per row: for each of n rows, the k with
+ * the largest s_k[k][row] (the first on ties); writes its S, stack and theta
+ * (theta_k [K][n][3]) to s_out, stack_out, theta_out [n][3]. */
+semb_status semb_best_of(int32_t K, int64_t n, const float *s_k, const float *stack_k, const float *theta_k,
+                         float *s_out, float *stack_out, float *theta_out, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Batched scan: CMP and CRS jobs of uneven fold and length in ONE persistent
  * launch (the paper processes CDPs as independent tasks, section 3.5; here

@@ -116,6 +116,10 @@ def lib():
         L.semb_scan_shape.restype = i32
         L.semb_clear_tuning.argtypes = []
         L.semb_clear_tuning.restype = None
+        L.semb_panel_peaks.argtypes = [P, i64, i32, i32, i32, i32, P, P, P]
+        L.semb_panel_peaks.restype = C.c_int
+        L.semb_best_of.argtypes = [i32, i64, P, P, P, P, P, P, P]
+        L.semb_best_of.restype = C.c_int
         L.semb_radius_apertures.argtypes = [P, P, i32, P, i32, C.c_double, P, P, P]
         L.semb_radius_apertures.restype = i64
         L.semb_kernel_timer_start.argtypes = [i32]
@@ -493,6 +497,44 @@ def refine(g: DeviceGathers, jobs: DeviceJobs, kind: int, theta, w: int, s_out, 
     _check(lib().semb_refine(C.byref(gs), C.byref(js), int(kind), _typed(theta, torch.float32, "theta"),
                              C.byref(o), int(w), _typed(s_out, torch.float32, "s_out"),
                              _typed(stack_out, torch.float32, "stack_out"), _stream(stream)))
+
+
+def panel_peaks(panel, nA: int, nB: int, nq: int, K: int, best_k, s_k, stream=None):
+    """The K best local maxima of each panel row (panel [n_rows, nA*nB*nq]);
+    best_k, s_k: [K, n_rows]."""
+    import torch
+    n = int(panel.shape[0])
+    _check(lib().semb_panel_peaks(_typed(panel, torch.float32, "panel"), n, int(nA), int(nB), int(nq), int(K),
+                                  _typed(best_k, torch.int32, "best_k"), _typed(s_k, torch.float32, "s_k"),
+                                  _stream(stream)))
+
+
+def best_of(s_k, stack_k, theta_k, s_out, stack_out, theta_out, stream=None):
+    """Per row, the candidate with the largest S among K: s_k, stack_k [K, n],
+    theta_k [K, n, 3] -> s_out, stack_out [n], theta_out [n, 3]."""
+    import torch
+    K, n = int(s_k.shape[0]), int(s_k.shape[1])
+    _check(lib().semb_best_of(K, n, _typed(s_k, torch.float32, "s_k"), _typed(stack_k, torch.float32, "stack_k"),
+                              _typed(theta_k, torch.float32, "theta_k"), _typed(s_out, torch.float32, "s_out"),
+                              _typed(stack_out, torch.float32, "stack_out"),
+                              _typed(theta_out, torch.float32, "theta_out"), _stream(stream)))
+
+
+def refine_multistart(g: DeviceGathers, jobs: DeviceJobs, kind: int, panel, A, B, q, w: int, K: int, theta_k,
+                      s_k, stack_k, best_k, peak_s, s_out, stack_out, theta_out, steps: int = 8,
+                      eta0: float = 0.5, scale=(1.0, 1.0, 1.0), lo=(-1e30, -1e30, -1e30), hi=(1e30, 1e30, 1e30),
+                      grow: float = 1.25, stream=None):
+    """Refinement from the K best local maxima of a coarse scan's panel: peaks,
+    K ascents, best of K.  Scratch tensors: theta_k [K, n, 3], s_k, stack_k
+    [K, n] (FP32), best_k [K, n] (int32), peak_s [K, n] (FP32)."""
+    nA = int(A.numel()) if A is not None else 1
+    nB = int(B.numel()) if B is not None else 1
+    panel_peaks(panel, nA, nB, int(q.numel()), K, best_k, peak_s, stream=stream)
+    for k in range(K):
+        theta_from_best(best_k[k], q, theta_k[k], A=A, B=B, stream=stream)
+        refine(g, jobs, kind, theta_k[k], w, s_k[k], stack_k[k], steps=steps, eta0=eta0, scale=scale, lo=lo,
+               hi=hi, grow=grow, stream=stream)
+    best_of(s_k, stack_k, theta_k, s_out, stack_out, theta_out, stream=stream)
 
 
 def _semblance_at_class():

@@ -611,6 +611,29 @@ semb_status semb_kernel_timer_stop(int32_t *count, float *ms, int32_t ms_len)
     return st;
 }
 
+semb_status semb_panel_peaks(const float *panel, int64_t n_rows, int32_t nA, int32_t nB, int32_t nq, int32_t K,
+                             int32_t *best_k, float *s_k, hipStream_t stream)
+{
+    if (n_rows < 0 || nA < 1 || nB < 1 || nq < 1 || K < 1 || K > 8)
+        return fail(SEMB_EINVAL, "semb_panel_peaks: n_rows >= 0, nA, nB, nq >= 1 and 1 <= K <= 8 are required");
+    if ((long long)nA * nB * nq > 0x7fffffffLL) return fail(SEMB_EINVAL, "semb_panel_peaks: grid too large");
+    if (n_rows == 0) return SEMB_OK;
+    if (!panel || !best_k || !s_k) return fail(SEMB_EINVAL, "semb_panel_peaks: panel, best_k and s_k are required");
+    return hip_status(semb::launch_panel_peaks(panel, n_rows, nA, nB, nq, K, best_k, s_k, stream),
+                      "semb_panel_peaks launch");
+}
+
+semb_status semb_best_of(int32_t K, int64_t n, const float *s_k, const float *stack_k, const float *theta_k,
+                         float *s_out, float *stack_out, float *theta_out, hipStream_t stream)
+{
+    if (K < 1 || n < 0) return fail(SEMB_EINVAL, "semb_best_of: K >= 1 and n >= 0 are required");
+    if (n == 0) return SEMB_OK;
+    if (!s_k || !stack_k || !theta_k || !s_out || !stack_out || !theta_out)
+        return fail(SEMB_EINVAL, "semb_best_of: every array is required");
+    return hip_status(semb::launch_best_of(K, n, s_k, stack_k, theta_k, s_out, stack_out, theta_out, stream),
+                      "semb_best_of launch");
+}
+
 const char *semb_shape_name(int32_t shape)
 {
     return (shape >= 0 && shape < semb::kScanShapes) ? kShapeNames[shape] : nullptr;

@@ -15,6 +15,9 @@
 // window sample, accumulates dS/dtau and scatters dS/dsample with float
 // atomics (every output sample's windows overlap those of its neighbours).
 
+#include <limits.h>
+#include <math.h>
+
 #include "internal.h"
 #include "traveltime.h"
 
@@ -303,6 +306,132 @@ __global__ void theta_from_best_kernel(const int32_t *best, int64_t n, const flo
     }
 }
 
+// ---------------------------------------------------------------------------
+// Starting points for a multi-start refinement: the K best local maxima of
+// each row of a semblance panel over its nA x nB x nq grid.  A cell is a
+// local maximum when every neighbour (diagonals included) is smaller, or
+// equal with a larger flat index, so a plateau yields one peak.  One wave per
+// row; lanes take cells lane, lane + 64, ...; each lane keeps its 8 best
+// peaks, then K rounds of a wave-wide argmax pick the row's K best (largest S,
+// then smallest index).  A row with fewer than K peaks repeats its best.
+// ---------------------------------------------------------------------------
+constexpr int PEAKS_KMAX = 8;
+
+__device__ __forceinline__ bool peak_better(float v, int c, float w, int d)
+{
+    return v > w || (v == w && c < d);
+}
+
+__global__ void __launch_bounds__(256)
+panel_peaks_kernel(const float *__restrict__ panel, int64_t n_rows, int nA, int nB, int nq, int K,
+                   int32_t *__restrict__ best_k, float *__restrict__ s_k)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+    if (row >= n_rows) return;  // uniform per wave; no barrier below
+    const int npar = nA * nB * nq;
+    const float *S = panel + row * (int64_t)npar;
+    float ts[PEAKS_KMAX];
+    int ti[PEAKS_KMAX];
+#pragma unroll
+    for (int k = 0; k < PEAKS_KMAX; ++k) {
+        ts[k] = -INFINITY;
+        ti[k] = INT_MAX;
+    }
+    for (int c = lane; c < npar; c += WAVE) {
+        const float v = S[c];
+        const int iq = c % nq, r = c / nq, iB = r % nB, iA = r / nB;
+        bool peak = true;
+        for (int da = -1; da <= 1; ++da) {
+            const int a = iA + da;
+            if (a < 0 || a >= nA) continue;
+            for (int db = -1; db <= 1; ++db) {
+                const int b = iB + db;
+                if (b < 0 || b >= nB) continue;
+                for (int dq = -1; dq <= 1; ++dq) {
+                    const int qq = iq + dq;
+                    if (qq < 0 || qq >= nq || (da == 0 && db == 0 && dq == 0)) continue;
+                    const int n = (a * nB + b) * nq + qq;
+                    if (peak_better(S[n], n, v, c)) peak = false;
+                }
+            }
+        }
+        if (peak && peak_better(v, c, ts[PEAKS_KMAX - 1], ti[PEAKS_KMAX - 1])) {
+            ts[PEAKS_KMAX - 1] = v;
+            ti[PEAKS_KMAX - 1] = c;
+#pragma unroll
+            for (int k = PEAKS_KMAX - 1; k > 0; --k) {
+                if (peak_better(ts[k], ti[k], ts[k - 1], ti[k - 1])) {
+                    const float tv = ts[k];
+                    const int tc = ti[k];
+                    ts[k] = ts[k - 1];
+                    ti[k] = ti[k - 1];
+                    ts[k - 1] = tv;
+                    ti[k - 1] = tc;
+                }
+            }
+        }
+    }
+    int first = 0;
+    float first_s = 0.f;
+    for (int k = 0; k < K; ++k) {
+        float bv = ts[0];
+        int bi = ti[0];
+#pragma unroll
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+            const float ov = __shfl_xor(bv, o, WAVE);
+            const int oi = __shfl_xor(bi, o, WAVE);
+            if (peak_better(ov, oi, bv, bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        if (ti[0] == bi && bi != INT_MAX) {  // the lane holding the winner drops it
+#pragma unroll
+            for (int j = 0; j < PEAKS_KMAX - 1; ++j) {
+                ts[j] = ts[j + 1];
+                ti[j] = ti[j + 1];
+            }
+            ts[PEAKS_KMAX - 1] = -INFINITY;
+            ti[PEAKS_KMAX - 1] = INT_MAX;
+        }
+        if (k == 0) {
+            first = bi;
+            first_s = bv;
+        }
+        if (lane == 0) {
+            const bool have = bi != INT_MAX;
+            best_k[(int64_t)k * n_rows + row] = have ? bi : first;
+            s_k[(int64_t)k * n_rows + row] = have ? bv : first_s;
+        }
+    }
+}
+
+// For each row, the candidate k with the largest s_k[k][row] (first on ties):
+// its S, stack and theta.
+__global__ void best_of_kernel(int K, int64_t n, const float *__restrict__ s_k, const float *__restrict__ stack_k,
+                               const float *__restrict__ theta_k, float *__restrict__ s_out,
+                               float *__restrict__ stack_out, float *__restrict__ theta_out)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int kb = 0;
+        float sb = s_k[i];
+        for (int k = 1; k < K; ++k) {
+            const float v = s_k[(int64_t)k * n + i];
+            if (v > sb) {
+                sb = v;
+                kb = k;
+            }
+        }
+        const int64_t src = (int64_t)kb * n + i;
+        s_out[i] = sb;
+        stack_out[i] = stack_k[src];
+        theta_out[3 * i + 0] = theta_k[3 * src + 0];
+        theta_out[3 * i + 1] = theta_k[3 * src + 1];
+        theta_out[3 * i + 2] = theta_k[3 * src + 2];
+    }
+}
+
 template <int KIND, bool GRAD, int W>
 hipError_t launch_pw(const PointArgs &a, hipStream_t stream)
 {
@@ -383,6 +512,27 @@ hipError_t launch_theta_from_best(const int32_t *best, int64_t n, const float *A
     const long long nb = (n + 255) / 256;
     hipLaunchKernelGGL(theta_from_best_kernel, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, stream, best,
                        n, A, nA, B, nB, q, nq, theta);
+    return hipGetLastError();
+}
+
+hipError_t launch_panel_peaks(const float *panel, int64_t n_rows, int nA, int nB, int nq, int K, int32_t *best_k,
+                              float *s_k, hipStream_t stream)
+{
+    if (n_rows <= 0) return hipSuccess;
+    const int64_t nb = (n_rows + 3) / 4;  // 4 waves (rows) per block
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(panel_peaks_kernel, dim3((unsigned)nb), dim3(4 * WAVE), 0, stream, panel, n_rows, nA, nB,
+                       nq, K, best_k, s_k);
+    return hipGetLastError();
+}
+
+hipError_t launch_best_of(int K, int64_t n, const float *s_k, const float *stack_k, const float *theta_k,
+                          float *s_out, float *stack_out, float *theta_out, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const long long nb = (n + 255) / 256;
+    hipLaunchKernelGGL(best_of_kernel, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, stream, K, n, s_k,
+                       stack_k, theta_k, s_out, stack_out, theta_out);
     return hipGetLastError();
 }
 
