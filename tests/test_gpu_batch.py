@@ -145,3 +145,25 @@ def test_batch_graph_replay():
         for a_, e_ in zip(got, eager):
             assert np.array_equal(a_, e_), f"replay {k} differs"
         del junk
+
+
+def test_batch_full_size_sampled():
+    """The whole 4096-gather batched line in the bench's configuration (split
+    256, one persistent launch); the oracle checks sampled rows of both kinds."""
+    import torch
+    bw = synth.batched_line()
+    _say("batched line generated")
+    b = Batch(bw, 256)
+    b.run()
+    torch.cuda.synchronize()
+    best, sb, st = b.outputs()
+    rng = np.random.default_rng(12)
+    for kind, grid, w, nrow in ((0, bw.grid_cmp, bw.w_cmp, 32), (1, bw.grid_crs, bw.w_crs, 12)):
+        sub = bw.subset(kind)
+        pick = rng.integers(0, sub.njobs, nrow)
+        rj = pick.astype(np.int32)
+        rs = np.array([rng.integers(0, int(bw.gathers.ns[sub.central[j]])) for j in pick], np.int32)
+        ref = oracle.scan_rows("cmp" if kind == 0 else "crs", bw.gathers, sub, grid, w, rj, rs)
+        rows = sub.out_off[rj] + rs
+        _say("full batch vs oracle", kind, gu.compare(f"full batch kind {kind}", (best, sb, st, None), ref,
+                                                      gu.sample_scale(bw.gathers, sub), rows))

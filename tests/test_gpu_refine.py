@@ -263,3 +263,41 @@ def test_multistart_refinement_is_never_worse():
     assert np.abs(Sm - Sref)[~fr].max() <= gu.S_TOL
     print(f"multi-start: mean S {single.mean():.4f} -> {Sm.mean():.4f}; rows improved {(Sm > single).mean():.3f}",
           flush=True)
+
+
+def test_refinement_full_line_sampled():
+    """The whole CRS line in the bench's configuration (coarse 7x7x11 scan, 8
+    steps); the oracle evaluates S and the stack at the refined parameters of
+    sampled rows, and S never fell below the coarse pick's."""
+    import torch
+    wl = synth.crs_line()
+    r = Refinement(wl)
+    r.run()
+    torch.cuda.synchronize()
+    s0 = r.s0.cpu().numpy()
+    S = r.S.cpu().numpy()
+    assert (S >= s0 - 1e-6).all()
+    rng = np.random.default_rng(13)
+    rows = rng.integers(0, r.n, 64)
+    th = r.theta.cpu().numpy().astype(np.float64)
+    # the oracle evaluates the sampled rows through a job list restricted to their jobs
+    jobs = wl.jobs
+    jsel = np.searchsorted(jobs.out_off, rows, side="right") - 1
+    uj = np.unique(jsel)
+    ptr, ag = [0], []
+    for j in uj:
+        ag.extend(jobs.apert_gather[jobs.apert_ptr[j]:jobs.apert_ptr[j + 1]])
+        ptr.append(len(ag))
+    ns = wl.gathers.ns[jobs.central[uj]].astype(np.int64)
+    off = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
+    sub = synth.Jobs(central=jobs.central[uj], apert_ptr=np.asarray(ptr, np.int32),
+                     apert_gather=np.asarray(ag, np.int32), out_off=off, n_out=int(ns.sum()))
+    th_sub = np.concatenate([th[jobs.out_off[j]:jobs.out_off[j] + int(wl.gathers.ns[jobs.central[j]])] for j in uj])
+    Sref, STref, _, fr = oracle.point("crs", wl.gathers, sub, th_sub, wl.w)
+    k = np.searchsorted(uj, jsel)
+    rsub = off[k] + (rows - jobs.out_off[jsel])
+    ok = ~fr[rsub]
+    assert np.abs(S[rows] - Sref[rsub])[ok].max() <= gu.S_TOL
+    scale = gu.sample_scale(wl.gathers, sub)[rsub]
+    assert (np.abs(r.st.cpu().numpy()[rows] - STref[rsub]) / scale)[ok].max() <= gu.STACK_TOL
+    _say(f"full-line refinement: {int(ok.sum())} sampled rows match the oracle")
