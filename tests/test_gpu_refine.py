@@ -270,13 +270,25 @@ def test_refinement_full_line_sampled():
     steps); the oracle evaluates S and the stack at the refined parameters of
     sampled rows, and S never fell below the coarse pick's."""
     import torch
+    import paper_1907_11678_amd as semb
     wl = synth.crs_line()
     r = Refinement(wl)
     r.run()
     torch.cuda.synchronize()
-    s0 = r.s0.cpu().numpy()
     S = r.S.cpu().numpy()
-    assert (S >= s0 - 1e-6).all()
+    # the ascent keeps a step only when S rises, measured in the point
+    # kernels' arithmetic: compare with S at the starting parameters in that
+    # same arithmetic (the scan's own S of the pick agrees with it to FP32
+    # rounding, well inside the 1e-5 parity bar, but not bit for bit)
+    th0 = torch.empty_like(r.theta)
+    semb.theta_from_best(r.best, r.q, th0, A=r.A, B=r.B)
+    S0 = torch.empty_like(r.S)
+    st0 = torch.empty_like(r.S)
+    semb.stack(r.dg, r.dj, 1, th0, wl.w, S0, st0)
+    torch.cuda.synchronize()
+    S0 = S0.cpu().numpy()
+    assert (S >= S0).all()
+    assert np.abs(S0 - r.s0.cpu().numpy()).max() <= 2 * gu.S_TOL
     rng = np.random.default_rng(13)
     rows = rng.integers(0, r.n, 64)
     th = r.theta.cpu().numpy().astype(np.float64)
