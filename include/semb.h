@@ -193,6 +193,19 @@ semb_status semb_theta_from_best(const int32_t *best, int64_t n_out, const float
                                  const float *B, int32_t nB, const float *q, int32_t nq, float *theta,
                                  hipStream_t stream);
 
+/* Gathers corrected along each output row's parameter theta[row] = (A, B, q)
+ * (the NMO / CRS correction at the picks, for quality control): for job j,
+ * aperture trace r (gathers as listed, traces in order) and output sample
+ * s < ns[central[j]],
+ *   out[corr_off[j] + r * ns[central[j]] + s] = f[k] + x (f[k+1] - f[k]),
+ * the trace read at the intersection tau of row out_off[j] + s's traveltime
+ * (k = floor(tau), x = tau - k; sections 2.1 / 2.2, Algorithm 1's
+ * interpolation), and 0 where T < 0 or samples k and k+1 are not both on the
+ * trace.  corr_off [njobs] (device int64) places each job's corrected traces;
+ * out (FP32) must hold them all.  CMP ignores A and B. */
+semb_status semb_corrected_gathers(const semb_gathers *g, const semb_jobs *jobs, int32_t kind, const float *theta,
+                                   const int64_t *corr_off, float *out, hipStream_t stream);
+
 /* Starting points for a multi-start refinement: for each of n_rows rows of a
  * semblance panel (FP32 [n_rows][nA * nB * nq], as a scan writes it), the K
  * (1 .. 8) largest local maxima over the nA x nB x nq grid, best first (flat

@@ -47,6 +47,8 @@ class Library:
         L.oracle_scan.argtypes = common + [P, i32, P, i32, P, i32, i32, P, P, P, P, P, P, C.c_int]
         L.oracle_point.argtypes = common + [P, i32, P, P, P, P, C.c_int]
         L.oracle_grad.argtypes = common + [P, P, i32, P, P, C.c_int]
+        L.oracle_corrected.argtypes = common + [P, P, P, C.c_int]
+        L.oracle_corrected.restype = C.c_int
         L.oracle_scan_rows.argtypes = [C.c_int, P, P, P, P, P, P, P, f64, i32, P, P, P, P, P,
                                        P, i32, P, i32, P, i32, i32, P, P, P, P, P, C.c_int]
         for f in (L.oracle_scan, L.oracle_point, L.oracle_grad, L.oracle_scan_rows):
@@ -215,6 +217,35 @@ def grad(kind, gs, jobs, theta: np.ndarray, g_s: np.ndarray, w: int, samples_gra
     if rc != 0:
         raise ValueError("oracle_grad: invalid arguments")
     return gt, gsm
+
+
+def corrected_offsets(gs, jobs) -> tuple[np.ndarray, int]:
+    """(corr_off [njobs], total): job j's corrected traces start at corr_off[j]
+    and hold (aperture traces) x (samples of its central gather) values."""
+    tp = np.asarray(gs.trace_ptr, np.int64)
+    off = np.zeros(jobs.njobs, np.int64)
+    tot = 0
+    for j in range(jobs.njobs):
+        ag = jobs.apert_gather[jobs.apert_ptr[j]:jobs.apert_ptr[j + 1]]
+        ntr = int((tp[ag + 1] - tp[ag]).sum())
+        off[j] = tot
+        tot += ntr * int(gs.ns[jobs.central[j]])
+    return off, tot
+
+
+def corrected(kind, gs, jobs, theta: np.ndarray, nthreads: int | None = None,
+              library: Library | None = None):
+    """The aperture traces of every job read along theta[row] (see
+    oracle_corrected); returns (values [total], corr_off [njobs])."""
+    a = _Args(kind, gs, jobs)
+    n = _n_out(jobs)
+    th = _c(theta, np.float64).reshape(n, 3)
+    off, tot = corrected_offsets(gs, jobs)
+    out = np.zeros(max(tot, 1), np.float64)
+    rc = (library or lib()).L.oracle_corrected(*a.head(), _p(th), _p(off), _p(out), int(nthreads or max_threads()))
+    if rc != 0:
+        raise ValueError("oracle_corrected: invalid arguments")
+    return out[:tot], off
 
 
 def theta_of(grid, flat: np.ndarray, kind) -> np.ndarray:

@@ -368,6 +368,62 @@ int oracle_point(int kind, const float *samples, const int64_t *sample_off, cons
     return 0;
 }
 
+/* Gathers corrected along each output row's parameter, for quality control:
+ * the traces of a job's aperture read at the intersection of the row's
+ * traveltime curve (CMP, section 2.1) or surface (CRS, section 2.2), by the
+ * linear interpolation of Algorithm 1 with a one-sample window.  For job j,
+ * aperture trace r (gathers as listed, traces in order) and output sample s:
+ *   out[corr_off[j] + r * ns_c + s] = f[k] + x (f[k+1] - f[k]),
+ * tau = sqrt(T(s dt, theta[out_off[j] + s])) / dt, k = floor(tau), x = tau - k,
+ * and 0 where T < 0 or samples k and k+1 are not both on the trace (the
+ * window rule with w = 1).  ns_c = samples of the central gather. */
+int oracle_corrected(int kind, const float *samples, const int64_t *sample_off, const int32_t *trace_ptr,
+                     const int32_t *ns, const float *half_offset, const float *midpoint,
+                     const float *central_x, double dt, int32_t njobs, const int32_t *job_central,
+                     const int32_t *apert_ptr, const int32_t *apert_gather, const int64_t *out_off,
+                     const double *theta, const int64_t *corr_off, double *out, int nthreads)
+{
+    gset g = {samples, sample_off, trace_ptr, ns, half_offset, midpoint, central_x, dt};
+    if (check_args(kind, &g, 1, 1, 1, 1)) return 1;
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (int j = 0; j < njobs; j++) {
+        const int c = job_central[j];
+        const int nsc = g.ns[c];
+        const double xc = (kind == ORACLE_CRS) ? (double)g.central_x[c] : 0.0;
+        int64_t r = 0;
+        for (int p = apert_ptr[j]; p < apert_ptr[j + 1]; p++) {
+            const int gg = apert_gather[p];
+            const int nsg = g.ns[gg];
+            for (int i = g.trace_ptr[gg]; i < g.trace_ptr[gg + 1]; i++, r++) {
+                const float *f = g.samples + g.sample_off[gg] + (int64_t)(i - g.trace_ptr[gg]) * nsg;
+                const double h = g.half_offset[i];
+                const double dm = (kind == ORACLE_CRS) ? (double)g.midpoint[i] - xc : 0.0;
+                double *o = out + corr_off[j] + r * nsc;
+                for (int s = 0; s < nsc; s++) {
+                    const int64_t row = out_off[j] + s;
+                    theta_t th = {theta[3 * row + 0], theta[3 * row + 1], theta[3 * row + 2]};
+                    if (kind == ORACLE_CMP) th.A = th.B = 0.0;
+                    double mag;
+                    const double T = traveltime_sq(kind, s * dt, th, dm, h, &mag);
+                    double v = 0.0;
+                    if (T >= 0.0) {
+                        const double tau = sqrt(T) / dt;
+                        if (window_on_trace(tau, 1, nsg)) {
+                            const double kf = floor(tau);
+                            const double frac = tau - kf;
+                            const int64_t k = (int64_t)kf;
+                            v = (double)f[k] + frac * ((double)f[k + 1] - (double)f[k]);
+                        }
+                    }
+                    o[s] = v;
+                }
+            }
+        }
+    }
+    return 0;
+}
+
 /*
  * Gradient of L = sum_rows g_s[row] * S(row, theta[row]) with respect to
  * theta (overwritten, [row][3] = dL/dA, dL/dB, dL/dq) and, if g_samples is

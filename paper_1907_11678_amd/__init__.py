@@ -116,6 +116,8 @@ def lib():
         L.semb_scan_shape.restype = i32
         L.semb_clear_tuning.argtypes = []
         L.semb_clear_tuning.restype = None
+        L.semb_corrected_gathers.argtypes = [P, P, i32, P, P, P, P]
+        L.semb_corrected_gathers.restype = C.c_int
         L.semb_panel_peaks.argtypes = [P, i64, i32, i32, i32, i32, P, P, P]
         L.semb_panel_peaks.restype = C.c_int
         L.semb_best_of.argtypes = [i32, i64, P, P, P, P, P, P, P]
@@ -497,6 +499,36 @@ def refine(g: DeviceGathers, jobs: DeviceJobs, kind: int, theta, w: int, s_out, 
     _check(lib().semb_refine(C.byref(gs), C.byref(js), int(kind), _typed(theta, torch.float32, "theta"),
                              C.byref(o), int(w), _typed(s_out, torch.float32, "s_out"),
                              _typed(stack_out, torch.float32, "stack_out"), _stream(stream)))
+
+
+def corrected_offsets(trace_ptr, ns, central, apert_ptr=None, apert_gather=None):
+    """(corr_off [njobs] int64, total) for semb_corrected_gathers: job j's
+    corrected traces take (aperture traces) x ns[central[j]] values.  Host
+    arrays (numpy)."""
+    import numpy as np
+    tp = np.asarray(trace_ptr, np.int64)
+    ns = np.asarray(ns, np.int64)
+    central = np.asarray(central, np.int64)
+    if apert_ptr is None:
+        ntr = tp[central + 1] - tp[central]
+    else:
+        ap = np.asarray(apert_ptr, np.int64)
+        ag = np.asarray(apert_gather, np.int64)
+        per = tp[ag + 1] - tp[ag]
+        csum = np.concatenate([[0], np.cumsum(per)])
+        ntr = csum[ap[1:]] - csum[ap[:-1]]
+    sizes = ntr * ns[central]
+    off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    return off, int(sizes.sum())
+
+
+def corrected_gathers(g: DeviceGathers, jobs: DeviceJobs, kind: int, theta, corr_off, out, stream=None):
+    """Every job's aperture traces read along theta[row] (see semb_corrected_gathers)."""
+    import torch
+    gs, js = g.cstruct(), jobs.cstruct()
+    _check(lib().semb_corrected_gathers(C.byref(gs), C.byref(js), int(kind), _typed(theta, torch.float32, "theta"),
+                                        _typed(corr_off, torch.int64, "corr_off"), _typed(out, torch.float32, "out"),
+                                        _stream(stream)))
 
 
 def panel_peaks(panel, nA: int, nB: int, nq: int, K: int, best_k, s_k, stream=None):

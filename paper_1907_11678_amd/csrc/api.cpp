@@ -611,6 +611,35 @@ semb_status semb_kernel_timer_stop(int32_t *count, float *ms, int32_t ms_len)
     return st;
 }
 
+semb_status semb_corrected_gathers(const semb_gathers *g, const semb_jobs *jobs, int32_t kind, const float *theta,
+                                   const int64_t *corr_off, float *out, hipStream_t stream)
+{
+    if (kind != SEMB_KIND_CMP && kind != SEMB_KIND_CRS) return fail(SEMB_EINVAL, "kind must be CMP or CRS");
+    const bool crs = kind == SEMB_KIND_CRS;
+    TRY(check_gathers(g, crs));
+    TRY(check_jobs(jobs, crs, g));
+    if (jobs->njobs == 0) return SEMB_OK;
+    if (!theta || !corr_off || !out) return fail(SEMB_EINVAL, "theta, corr_off and out are required");
+    semb::PointArgs a{};
+    a.samples = g->samples;
+    a.sample_off = g->sample_off;
+    a.trace_ptr = g->trace_ptr;
+    a.ns = g->ns;
+    a.half_offset = g->half_offset;
+    a.midpoint = g->midpoint;
+    a.central_x = g->central_x;
+    a.dt = g->dt;
+    a.central = jobs->central;
+    a.apert_ptr = crs ? jobs->apert_ptr : nullptr;
+    a.apert_gather = crs ? jobs->apert_gather : nullptr;
+    a.out_off = jobs->out_off;
+    a.njobs = jobs->njobs;
+    a.n_sblk = (g->ns_max + 63) / 64;
+    a.theta = theta;
+    a.w = 1;
+    return hip_status(semb::launch_corrected(kind, a, corr_off, out, stream), "semb_corrected_gathers launch");
+}
+
 semb_status semb_panel_peaks(const float *panel, int64_t n_rows, int32_t nA, int32_t nB, int32_t nq, int32_t K,
                              int32_t *best_k, float *s_k, hipStream_t stream)
 {

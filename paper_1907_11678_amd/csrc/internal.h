@@ -131,6 +131,7 @@ hipError_t launch_batch(const BatchArgs &a, int ngroups, hipStream_t stream);
 hipError_t launch_point(int kind, const PointArgs &a, hipStream_t stream);
 hipError_t launch_grad(int kind, const PointArgs &a, hipStream_t stream);
 hipError_t launch_refine(int kind, const PointArgs &a, const RefineArgs &o, hipStream_t stream);
+hipError_t launch_corrected(int kind, const PointArgs &a, const int64_t *corr_off, float *out, hipStream_t stream);
 hipError_t launch_panel_peaks(const float *panel, int64_t n_rows, int nA, int nB, int nq, int K, int32_t *best_k,
                               float *s_k, hipStream_t stream);
 hipError_t launch_best_of(int K, int64_t n, const float *s_k, const float *stack_k, const float *theta_k,

@@ -306,6 +306,40 @@ __global__ void theta_from_best_kernel(const int32_t *best, int64_t n, const flo
     }
 }
 
+// Gathers corrected along each output sample's parameter (quality control):
+// lane l reads every aperture trace at the intersection of its row, with the
+// interpolation of a one-sample window, and writes it to the job's corrected
+// trace (coalesced across lanes); 0 where the trace does not contribute.
+template <int KIND>
+__global__ void __launch_bounds__(WAVE)
+corrected_kernel(PointArgs a, const int64_t *__restrict__ corr_off, float *__restrict__ out)
+{
+    int job, s;
+    const int64_t row = my_row<KIND>(a, job, s);
+    if (row < 0) return;
+    const RowCtx r = row_ctx<KIND>(a, job);
+    const int nsc = a.ns[r.c];
+    const double A = (KIND == SEMB_KIND_CRS) ? (double)a.theta[3 * row + 0] : 0.0;
+    const double B = (KIND == SEMB_KIND_CRS) ? (double)a.theta[3 * row + 1] : 0.0;
+    const double q = (double)a.theta[3 * row + 2];
+    float *o = out + corr_off[job] + s;
+    for (int k = r.k0; k < r.k1; ++k) {
+        const int g = r.ag ? r.ag[k] : r.c;
+        const int nsg = a.ns[g];
+        const int tb = a.trace_ptr[g], te = a.trace_ptr[g + 1];
+        for (int i = tb; i < te; ++i, o += nsc) {
+            const float dmf = (KIND == SEMB_KIND_CRS) ? (float)((double)a.midpoint[i] - r.xc) : 0.f;
+            const Isect hit = intersect<KIND, 1>(s, A, B, q, a.half_offset[i], dmf, r.inv_dt, nsg);
+            float v = 0.f;
+            if (hit.valid) {
+                const float *f = a.samples + a.sample_off[g] + (int64_t)(i - tb) * nsg + hit.a;
+                v = fmaf(hit.x, f[1] - f[0], f[0]);
+            }
+            *o = v;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Starting points for a multi-start refinement: the K best local maxima of
 // each row of a semblance panel over its nA x nB x nq grid.  A cell is a
@@ -512,6 +546,19 @@ hipError_t launch_theta_from_best(const int32_t *best, int64_t n, const float *A
     const long long nb = (n + 255) / 256;
     hipLaunchKernelGGL(theta_from_best_kernel, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, stream, best,
                        n, A, nA, B, nB, q, nq, theta);
+    return hipGetLastError();
+}
+
+hipError_t launch_corrected(int kind, const PointArgs &a, const int64_t *corr_off, float *out, hipStream_t stream)
+{
+    const long long nblk = (long long)a.njobs * a.n_sblk;
+    if (nblk == 0) return hipSuccess;
+    if (kind == SEMB_KIND_CMP)
+        hipLaunchKernelGGL((corrected_kernel<SEMB_KIND_CMP>), dim3((unsigned)nblk), dim3(WAVE), 0, stream, a,
+                           corr_off, out);
+    else
+        hipLaunchKernelGGL((corrected_kernel<SEMB_KIND_CRS>), dim3((unsigned)nblk), dim3(WAVE), 0, stream, a,
+                           corr_off, out);
     return hipGetLastError();
 }
 

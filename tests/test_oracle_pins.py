@@ -353,9 +353,67 @@ def pin_crs_reduces_to_cmp(lib=None):
     return bad
 
 
+def pin_corrected(lib=None):
+    """Gathers corrected along a parameter (oracle.corrected):
+    (1) q = 0 (and A = B = 0 for CRS): tau = s, so every trace comes back
+        unchanged, except its last sample, which has no successor and reads 0;
+    (2) at the true velocity an integer-aligned event lands on its zero-offset
+        sample in every trace, so the corrected gather is flat there: every
+        trace reads the wavelet's peak amplitude;
+    (3) with a one-sample window the point evaluation's stack is the mean of
+        the corrected values over the contributing traces."""
+    bad = []
+    gs = _tiny_line(4)
+    for kind, jobs in (("cmp", synth.cmp_jobs(gs)), ("crs", synth.line_crs_jobs(gs, [1, 2, 3], 1))):
+        th = np.zeros((jobs.n_out, 3))
+        out, off = oracle.corrected(kind, gs, jobs, th, library=lib)
+        for j in range(jobs.njobs):
+            c = int(jobs.central[j])
+            nsc = int(gs.ns[c])
+            r = 0
+            for g in jobs.apert_gather[jobs.apert_ptr[j]:jobs.apert_ptr[j + 1]]:
+                for li in range(int(gs.trace_ptr[g + 1] - gs.trace_ptr[g])):
+                    f = gs.trace(int(g), li).astype(np.float64)
+                    want = np.zeros(nsc)
+                    m = min(nsc, f.size - 1)
+                    want[:m] = f[:m]
+                    got = out[off[j] + r * nsc: off[j] + (r + 1) * nsc]
+                    if np.abs(got - want).max(initial=0.0) > 1e-12:
+                        bad.append(f"corrected identity {kind} job {j} trace {r}")
+                    r += 1
+    dt, ns = 0.004, 600
+    traces, h, s_e = _aligned_cmp_gather(2500.0, 1.0, dt, ns, [0, 3, 7, 12, 20, 31], amp=0.8)
+    ag = synth.pack_gathers([traces], [h], [np.zeros(len(h))], [0.0], dt)
+    aj = synth.cmp_jobs(ag)
+    th = np.zeros((aj.n_out, 3))
+    th[:, 2] = float(np.float32(4.0 / 2500.0 ** 2))
+    out, off = oracle.corrected("cmp", ag, aj, th, library=lib)
+    at = out.reshape(len(h), ns)[:, s_e]
+    if np.abs(at - 0.8 * synth.ricker(np.zeros(1), 25.0)[0]).max() > 1e-6:
+        bad.append(f"corrected aligned event not flat at its peak: {at}")
+    for kind, jobs in (("cmp", synth.cmp_jobs(gs)), ("crs", synth.line_crs_jobs(gs, [1, 2, 3], 1))):
+        rng = np.random.default_rng(8)
+        th = np.zeros((jobs.n_out, 3))
+        th[:, 2] = 4.0 / rng.uniform(600, 2400, jobs.n_out) ** 2
+        if kind == "crs":
+            th[:, 0] = rng.uniform(-2e-3, 2e-3, jobs.n_out)
+            th[:, 1] = rng.uniform(-2e-5, 2e-5, jobs.n_out)
+        out, off = oracle.corrected(kind, gs, jobs, th, library=lib)
+        _, stack1, m1, _ = oracle.point(kind, gs, jobs, th, 1, library=lib)
+        for j in range(jobs.njobs):
+            nsc = int(gs.ns[jobs.central[j]])
+            ag_ = jobs.apert_gather[jobs.apert_ptr[j]:jobs.apert_ptr[j + 1]]
+            ntr = int(sum(gs.trace_ptr[g + 1] - gs.trace_ptr[g] for g in ag_))
+            tot = out[off[j]: off[j] + ntr * nsc].reshape(ntr, nsc).sum(axis=0)
+            rows = slice(int(jobs.out_off[j]), int(jobs.out_off[j]) + nsc)
+            if np.abs(tot - stack1[rows] * m1[rows]).max(initial=0.0) > 1e-12:
+                bad.append(f"corrected {kind} job {j}: sum differs from the w = 1 stack x M")
+    return bad
+
+
 PINS = [pin_hand_cases, pin_zero_moveout_closed_form, pin_ramp_traces, pin_aligned_ricker_cmp,
         pin_aligned_ricker_crs, pin_tie_break, pin_brute_force, pin_gradient_fd,
-        pin_crs_reduces_to_cmp]
+        pin_crs_reduces_to_cmp, pin_corrected]
 
 
 # --------------------------------------------------------------------------
@@ -429,6 +487,13 @@ def test_invalid_arguments_rejected():
 # mutation check: every plausible slip in the oracle must break a pin
 # --------------------------------------------------------------------------
 MUTATIONS = [
+    ("corrected interpolation sign", "v = (double)f[k] + frac * ((double)f[k + 1] - (double)f[k]);",
+     "v = (double)f[k] - frac * ((double)f[k + 1] - (double)f[k]);"),
+    ("corrected time origin", "traveltime_sq(kind, s * dt, th, dm, h, &mag);",
+     "traveltime_sq(kind, (s + 1) * dt, th, dm, h, &mag);"),
+    ("corrected displacement", "const double dm = (kind == ORACLE_CRS) ? (double)g.midpoint[i] - xc : 0.0;\n"
+     "                double *o", "const double dm = (kind == ORACLE_CRS) ? (double)g.midpoint[i] : 0.0;\n"
+     "                double *o"),
     ("interpolation sign", "const double v = f0 + x * (f1 - f0);\n                U[j]",
      "const double v = f0 + x * (f0 - f1);\n                U[j]"),
     ("interpolation index", "const double f0 = f[a + j], f1 = f[a + j + 1];\n            "
