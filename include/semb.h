@@ -116,6 +116,8 @@ typedef struct semb_outputs {
     float *s_best;  /* [n_out] its semblance                                        */
     float *stack;   /* [n_out] its stacked amplitude                                */
     float *panel;   /* [n_out * n_params] every semblance, or NULL                  */
+    void *panel_f16; /* [n_out * n_params] the same in IEEE FP16 (round to nearest
+                        even): half the bytes of the FP32 panel; or NULL          */
 } semb_outputs;
 
 #define SEMB_W_MAX 31          /* largest window; w must be odd, 1 .. SEMB_W_MAX */

@@ -50,7 +50,7 @@ class CJobs(C.Structure):
 
 class COutputs(C.Structure):
     _fields_ = [("best", C.c_void_p), ("s_best", C.c_void_p), ("stack", C.c_void_p),
-                ("panel", C.c_void_p)]
+                ("panel", C.c_void_p), ("panel_f16", C.c_void_p)]
 
 
 class CRefineOpts(C.Structure):
@@ -297,27 +297,29 @@ def upload_jobs(central, apert_ptr, apert_gather, out_off, n_out, device="cuda")
 # ---------------------------------------------------------------------------
 # the four calls
 # ---------------------------------------------------------------------------
-def _outputs(best, s_best, stack_out, panel) -> COutputs:
+def _outputs(best, s_best, stack_out, panel, panel_f16=None) -> COutputs:
     import torch
     return COutputs(_typed(best, torch.int32, "best"), _typed(s_best, torch.float32, "s_best"),
-                    _typed(stack_out, torch.float32, "stack"), _typed(panel, torch.float32, "panel"))
+                    _typed(stack_out, torch.float32, "stack"), _typed(panel, torch.float32, "panel"),
+                    _typed(panel_f16, torch.float16, "panel_f16"))
 
 
 def cmp_scan(g: DeviceGathers, jobs: DeviceJobs, q, w: int, best, s_best, stack_out, ws,
-             panel=None, stream=None):
-    """Enqueue the CMP scan; results land in best / s_best / stack_out (/ panel)."""
+             panel=None, stream=None, panel_f16=None):
+    """Enqueue the CMP scan; results land in best / s_best / stack_out (/ panel,
+    panel_f16)."""
     import torch
-    gs, js, out = g.cstruct(), jobs.cstruct(), _outputs(best, s_best, stack_out, panel)
+    gs, js, out = g.cstruct(), jobs.cstruct(), _outputs(best, s_best, stack_out, panel, panel_f16)
     _check(lib().cmp_scan(C.byref(gs), C.byref(js), _typed(q, torch.float32, "q"), int(q.numel()),
                           int(w), C.byref(out), _ptr(ws), int(ws.numel() * ws.element_size()),
                           _stream(stream)))
 
 
 def crs_scan(g: DeviceGathers, jobs: DeviceJobs, A, B, q, w: int, best, s_best, stack_out, ws,
-             panel=None, stream=None):
+             panel=None, stream=None, panel_f16=None):
     """Enqueue the 2D CRS scan (flat parameter index (iA*nB + iB)*nq + iq)."""
     import torch
-    gs, js, out = g.cstruct(), jobs.cstruct(), _outputs(best, s_best, stack_out, panel)
+    gs, js, out = g.cstruct(), jobs.cstruct(), _outputs(best, s_best, stack_out, panel, panel_f16)
     _check(lib().crs_scan(C.byref(gs), C.byref(js), _typed(A, torch.float32, "A"), int(A.numel()),
                           _typed(B, torch.float32, "B"), int(B.numel()),
                           _typed(q, torch.float32, "q"), int(q.numel()), int(w), C.byref(out),

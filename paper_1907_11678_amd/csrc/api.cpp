@@ -255,6 +255,7 @@ semb_status scan_common(int kind, const semb_gathers *g, const semb_jobs *jobs, 
     a.s_best = out->s_best;
     a.stack = out->stack;
     a.panel = out->panel;
+    a.panel16 = out->panel_f16;
     const int sid = shape >= 0 ? shape : chosen_shape(kind, w, g, jobs);
     return hip_status(timed(stream, [&] { return semb::launch_scan(kind, a, sid, stream); }),
                       crs ? "crs_scan launch" : "cmp_scan launch");
@@ -429,7 +430,8 @@ semb_status scan_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_
     if (ntiles < 0 || ngroups < 0 || nparts < 0) return fail(SEMB_EINVAL, "negative plan sizes");
     if (ntiles > 0 && !tiles) return fail(SEMB_EINVAL, "tiles is NULL");
     if (!out || !out->best || !out->s_best || !out->stack) return fail(SEMB_EINVAL, "outputs are required");
-    if (out->panel) return fail(SEMB_EINVAL, "scan_batch writes no panel (panel must be NULL)");
+    if (out->panel || out->panel_f16)
+        return fail(SEMB_EINVAL, "scan_batch writes no panel (panel and panel_f16 must be NULL)");
     const BatchLayout lay = batch_layout(g->nsamples, b->w_cmp, b->w_crs, ngroups, nparts);
     if (!ws || ws_bytes < lay.total || ((uintptr_t)ws % kAlign) != 0)
         return fail(SEMB_EWORKSPACE, "workspace must be %zu bytes, 256-byte aligned (got %zu at %p)", lay.total,

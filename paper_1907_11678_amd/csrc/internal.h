@@ -54,6 +54,7 @@ struct ScanArgs {
     float *s_best;
     float *stack;
     float *panel;
+    void *panel16;
 };
 
 // One partial pick of a split tile: best S, its flat index, its stack.

@@ -133,10 +133,10 @@ batch_kernel(BatchArgs b)
         int bI;
         if (kind == SEMB_KIND_CMP)
             scan_tile<SEMB_KIND_CMP, WC, BATCH_P_CMP, BATCH_NW, BATCH_CAP, BATCH_TMAX, true>(
-                b.g, b.j, b.pc, L.c, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, bS, bI, bSt);
+                b.g, b.j, b.pc, L.c, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, nullptr, bS, bI, bSt);
         else
             scan_tile<SEMB_KIND_CRS, WR, BATCH_P_CRS, BATCH_NW, BATCH_CAP, BATCH_TMAX, false>(
-                b.g, b.j, b.pr, L.r, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, bS, bI, bSt);
+                b.g, b.j, b.pr, L.r, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, nullptr, bS, bI, bSt);
         const int64_t row = b.j.out_off[tl.job] + tl.sblk * WAVE + lane;
         if (tl.nsplit <= 1) {
             if (threadIdx.x < WAVE && bS >= 0.f) {

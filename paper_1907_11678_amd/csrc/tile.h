@@ -42,6 +42,8 @@
 
 #pragma once
 
+#include <hip/hip_fp16.h>
+
 #include "internal.h"
 #include "traveltime.h"
 
@@ -158,11 +160,13 @@ __device__ __forceinline__ void load_traces(const GatherView &g, LDS &L, int na,
 // All threads of the workgroup call this together.  On return, lane l of
 // wave 0 holds the pick of output sample 64*sblk + l over [pbeg, pend):
 // bS (negative if the lane's sample lies beyond the job's trace length), bI,
-// bSt.  panel: optional [row][npar] semblance of every cell.
+// bSt.  panel / panel16: optional [row][npar] semblance of every cell, FP32
+// and FP16 (round to nearest even).
 template <int KIND, int W, int P, int NW, int CAP, int TMAX, bool BRANCHY>
 __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv, const ParamView &pv,
                                           StageLds<KIND, W, P, NW, CAP, TMAX> &L, int job, int sblk, int pbeg,
-                                          int pend, float *panel, float &bS, int &bI, float &bSt)
+                                          int pend, float *panel, __half *panel16, float &bS, int &bI,
+                                          float &bSt)
 {
     constexpr int HW = (W - 1) / 2;
     constexpr int NT = NW * P;  // parameters per block
@@ -474,6 +478,7 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                     const float S = (Mc[p] > 0.f && D[p] > 0.f) ? N / (Mc[p] * D[p]) : 0.f;
                     const float st = (Mc[p] > 0.f) ? Ls / (Mc[p] * (float)W) : 0.f;
                     if (panel) panel[row * pv.npar + th] = S;
+                    if (panel16) panel16[row * pv.npar + th] = __float2half(S);
                     if (S > bS) {  // parameters visited in increasing index: first max wins
                         bS = S;
                         bI = th;
@@ -577,7 +582,8 @@ scan_kernel(ScanArgs a)
     float bS, bSt;
     int bI;
     scan_tile<KIND, W, S::P, S::NW, S::CAP, S::TMAX, S::BRANCHY>(a.g, a.j, a.p, L, job, sblk, 0, a.p.npar,
-                                                                   a.panel, bS, bI, bSt);
+                                                                   a.panel, static_cast<__half *>(a.panel16), bS, bI,
+                                                                   bSt);
     const int lane = threadIdx.x & (WAVE - 1);
     if (threadIdx.x < WAVE && bS >= 0.f) {
         const int64_t row = a.j.out_off[job] + sblk * WAVE + lane;

@@ -249,3 +249,27 @@ def test_crs_line_full_size_sampled():
     ref = oracle.scan_rows("crs", wl.gathers, wl.jobs, wl.grid, wl.w, rj, rs)
     rows = wl.jobs.out_off[rj] + rs
     _say("crs full", gu.compare("crs_line_full", gpu, ref, gu.sample_scale(wl.gathers, wl.jobs), rows))
+
+
+@pytest.mark.parametrize("kind", ["cmp", "crs"])
+def test_fp16_panel_is_the_rounded_fp32_panel(kind):
+    import torch
+    import paper_1907_11678_amd as semb
+    wl = synth.cmp_plain(ids=[2]) if kind == "cmp" else synth.crs_line(centrals=[50], grid=synth.crs_coarse_grid())
+    dg, dj = gu.device_inputs(wl.gathers, wl.jobs)
+    n = wl.jobs.n_out
+    npar = wl.grid.n if kind == "crs" else wl.grid.q.size
+    best = torch.empty(n, dtype=torch.int32, device="cuda")
+    sb = torch.empty(n, device="cuda")
+    st = torch.empty(n, device="cuda")
+    p32 = torch.empty((n, npar), device="cuda")
+    p16 = torch.full((n, npar), float("nan"), dtype=torch.float16, device="cuda")
+    ws = semb.alloc_workspace(dg.nsamples)
+    q = torch.from_numpy(wl.grid.q).cuda()
+    if kind == "cmp":
+        semb.cmp_scan(dg, dj, q, wl.w, best, sb, st, ws, panel=p32, panel_f16=p16)
+    else:
+        semb.crs_scan(dg, dj, torch.from_numpy(wl.grid.A).cuda(), torch.from_numpy(wl.grid.B).cuda(), q, wl.w,
+                      best, sb, st, ws, panel=p32, panel_f16=p16)
+    torch.cuda.synchronize()
+    assert torch.equal(p16, p32.half())
