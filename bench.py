@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cmp-only", action="store_true", help="skip the CRS, batched and refinement legs")
+    ap.add_argument("--legs", default="crs,refine,batched",
+                    help="legs to run after the CMP step (comma list of crs, refine, batched)")
     ap.add_argument("--gathers", type=int, default=20000, help="(testing only) fewer CMP gathers")
     ap.add_argument("--cpu-gathers", type=int, default=384, help="CMP gathers in the CPU oracle sample")
     ap.add_argument("--paper-shapes", action="store_true",
@@ -251,11 +253,14 @@ def main():
     del dg, ws, host
     torch.cuda.empty_cache()
 
-    if not args.cmp_only:
+    legs = set() if args.cmp_only else {x.strip() for x in args.legs.split(",") if x.strip()}
+    if legs & {"crs", "refine"}:
         out["crs"], fine = crs_leg(torch, synth, semb, dev, stream)
-        out["refine"] = refine_leg(torch, synth, semb, dev, stream, fine)
+        if "refine" in legs:
+            out["refine"] = refine_leg(torch, synth, semb, dev, stream, fine)
         del fine
         torch.cuda.empty_cache()
+    if "batched" in legs:
         out["batched"] = batched_leg(torch, synth, semb, dev, stream)
 
     if args.paper_shapes:

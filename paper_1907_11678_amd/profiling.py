@@ -9,6 +9,11 @@ record of a kernel.
         The same per (kernel, grid size), so that full launches and a
         tuner's sample launches of one kernel are told apart.
 
+    python -m paper_1907_11678_amd.profiling counters <kernel-substring> <evals> <csv> [<csv> ...]
+        SQ counters of the largest-grid dispatches of a kernel from
+        `rocprofv3 --pmc` runs, and the instruction counts per 64-lane
+        evaluation, LDS busy fraction and wave wait fraction.
+
     python -m paper_1907_11678_amd.profiling traffic <fetch_csv> <write_csv>
             <kernel-substring> <copy-bytes> <out.txt>
         Reduce two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs
@@ -124,6 +129,49 @@ def traffic_record(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int)
     }
 
 
+def counter_summary(csvs, kernel: str, evals: int) -> dict:
+    """Per-launch SQ counters of the largest-grid dispatches of `kernel` from
+    one or more `rocprofv3 --pmc` counter_collection.csv files, and the rates
+    per 64-lane evaluation (evals = intersections per launch)."""
+    acc = defaultdict(float)
+    nl = defaultdict(int)
+    gui = []
+    for path in csvs:
+        rows = list(csv.DictReader(open(path)))
+        grids = [int(r["Grid_Size"]) for r in rows if kernel in r["Kernel_Name"]]
+        if not grids:
+            raise SystemExit(f"{path}: no dispatch of {kernel!r}")
+        gmax = max(grids)
+        seen = defaultdict(set)
+        for r in rows:
+            if kernel not in r["Kernel_Name"] or int(r["Grid_Size"]) != gmax:
+                continue
+            c = r["Counter_Name"]
+            acc[c] += float(r["Counter_Value"])
+            seen[c].add(r["Dispatch_Id"])
+        for c, d in seen.items():
+            nl[c] = len(d)
+        if "GRBM_GUI_ACTIVE" in seen:
+            gui.append(acc.pop("GRBM_GUI_ACTIVE") / nl["GRBM_GUI_ACTIVE"])
+    per = {c: v / max(nl[c], 1) for c, v in acc.items()}
+    we = evals / 64.0
+    out = {"counters_per_launch": per, "wave_evals_per_launch": we}
+    if "SQ_INSTS_VALU" in per:
+        out["valu_insts_per_wave_eval"] = per["SQ_INSTS_VALU"] / we
+    if "SQ_INSTS_LDS" in per:
+        out["lds_insts_per_wave_eval"] = per["SQ_INSTS_LDS"] / we
+    if gui:
+        cyc = sum(gui) / len(gui) / 8.0  # GRBM_GUI_ACTIVE is summed over the 8 XCDs
+        out["gpu_cycles_per_launch"] = cyc
+        if "SQ_LDS_IDX_ACTIVE" in per:
+            out["lds_busy_fraction"] = per["SQ_LDS_IDX_ACTIVE"] / (cyc * 256)
+        if "SQ_LDS_BANK_CONFLICT" in per and "SQ_LDS_IDX_ACTIVE" in per:
+            out["lds_bank_conflict_fraction"] = per["SQ_LDS_BANK_CONFLICT"] / per["SQ_LDS_IDX_ACTIVE"]
+    if "SQ_WAIT_ANY" in per and "SQ_WAVE_CYCLES" in per:
+        out["wave_wait_fraction"] = per["SQ_WAIT_ANY"] / per["SQ_WAVE_CYCLES"]
+    return out
+
+
 def write_record(rec: dict, path: str, header: str = ""):
     with open(path, "w") as f:
         if header:
@@ -157,6 +205,9 @@ def main(argv):
         print(kernel_stats_table(argv[1]))
     elif len(argv) >= 2 and argv[0] == "trace":
         print(kernel_trace_table(argv[1]))
+    elif len(argv) >= 4 and argv[0] == "counters":
+        import json
+        print(json.dumps(counter_summary(argv[3:], argv[1], int(float(argv[2]))), indent=1))
     elif len(argv) == 6 and argv[0] == "traffic":
         rec = traffic_record(argv[1], argv[2], argv[3], int(argv[4]))
         write_record(rec, argv[5])
