@@ -166,6 +166,7 @@ def main():
 
     # ---- CMP large: the step ---------------------------------------------
     spec = synth.cmp_large_spec()
+    full_size = args.gathers == spec.ngathers
     spec.ngathers = args.gathers
     G, F, NS, W = spec.ngathers, spec.fold, spec.ns, 15
     t = time.time()
@@ -213,7 +214,8 @@ def main():
     value = evals / (wall / args.steps)
     k_avg = sum(kt.ms) / len(kt.ms) * 1e-3
     achieved = flops / k_avg / 1e12
-    traffic = profiling.current_traffic(TRAFFIC_RECORD)
+    # the record holds the full workload's per-launch bytes: a reduced run has none
+    traffic = profiling.current_traffic(TRAFFIC_RECORD) if full_size else None
     log(f"cmp_large: {ms_per_step:.1f} ms/step, scan kernel {[round(x, 1) for x in kt.ms]} ms, "
         f"{value:.3e} evals/s, valid fraction {valid / evals:.4f}, {achieved:.1f} TFLOP/s")
 

@@ -167,6 +167,15 @@ def counter_summary(csvs, kernel: str, evals: int) -> dict:
             out["lds_busy_fraction"] = per["SQ_LDS_IDX_ACTIVE"] / (cyc * 256)
         if "SQ_LDS_BANK_CONFLICT" in per and "SQ_LDS_IDX_ACTIVE" in per:
             out["lds_bank_conflict_fraction"] = per["SQ_LDS_BANK_CONFLICT"] / per["SQ_LDS_IDX_ACTIVE"]
+    if "SQ_INSTS_LDS_LOAD_BANDWIDTH" in per:
+        # the counter is in 64-byte units of bytes read by LDS instructions
+        lb = per["SQ_INSTS_LDS_LOAD_BANDWIDTH"] * 64.0
+        out["lds_load_bytes_per_launch"] = lb
+        out["lds_load_bytes_per_lane_eval"] = lb / evals
+        if gui:
+            out["lds_load_bytes_per_clk_per_cu"] = lb / (out["gpu_cycles_per_launch"] * 256)
+    if "SQ_ACTIVE_INST_VALU2" in per and "SQ_ACTIVE_INST_VALU" in per:
+        out["valu_dual_issue_fraction"] = per["SQ_ACTIVE_INST_VALU2"] / per["SQ_ACTIVE_INST_VALU"]
     if "SQ_WAIT_ANY" in per and "SQ_WAVE_CYCLES" in per:
         out["wave_wait_fraction"] = per["SQ_WAIT_ANY"] / per["SQ_WAVE_CYCLES"]
     return out
