@@ -142,17 +142,19 @@ def counter_summary(csvs, kernel: str, evals: int) -> dict:
         if not grids:
             raise SystemExit(f"{path}: no dispatch of {kernel!r}")
         gmax = max(grids)
+        part = defaultdict(float)
         seen = defaultdict(set)
         for r in rows:
             if kernel not in r["Kernel_Name"] or int(r["Grid_Size"]) != gmax:
                 continue
             c = r["Counter_Name"]
-            acc[c] += float(r["Counter_Value"])
+            part[c] += float(r["Counter_Value"])
             seen[c].add(r["Dispatch_Id"])
-        for c, d in seen.items():
-            nl[c] = len(d)
-        if "GRBM_GUI_ACTIVE" in seen:
-            gui.append(acc.pop("GRBM_GUI_ACTIVE") / nl["GRBM_GUI_ACTIVE"])
+        if "GRBM_GUI_ACTIVE" in part:  # one value per pass, averaged over the passes below
+            gui.append(part.pop("GRBM_GUI_ACTIVE") / len(seen.pop("GRBM_GUI_ACTIVE")))
+        for c, v in part.items():
+            acc[c] += v
+            nl[c] += len(seen[c])
     per = {c: v / max(nl[c], 1) for c, v in acc.items()}
     we = evals / 64.0
     out = {"counters_per_launch": per, "wave_evals_per_launch": we}
