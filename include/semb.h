@@ -264,7 +264,7 @@ typedef struct semb_batch_host {
 } semb_batch_host;
 
 /* Build the tile list (at most split_params parameters per tile, rounded up to
- * a multiple of 16).  tiles may be NULL to query the count.  On success
+ * a multiple of 32).  tiles may be NULL to query the count.  On success
  * returns the number of tiles and sets *ngroups and *nparts (partial slots);
  * returns -1 (see semb_last_error) on invalid input or if max_tiles is too
  * small.  [host] */

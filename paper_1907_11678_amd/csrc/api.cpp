@@ -301,7 +301,7 @@ semb_status point_common(bool grad, const semb_gathers *g, const semb_jobs *jobs
     return hip_status(timed(stream, [&] { return semb::launch_point(kind, a, stream); }), "stack launch");
 }
 
-constexpr int kBatchBlock = 16;  // parameters per block of the batch kernel (8 waves x 2)
+constexpr int kBatchBlock = 32;  // parameters per CRS block of the batch kernel (8 waves x 4)
 
 bool batch_w_ok(int w) { return w == 9 || w == 11 || w == 15; }
 

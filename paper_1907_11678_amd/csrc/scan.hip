@@ -94,13 +94,17 @@ hipError_t launch_energy_w(const float *samples, const int64_t *sample_off, cons
 // tile that covers all parameters of its (job, sample block) writes the
 // outputs; otherwise it stores a partial pick, and the last tile of its group
 // to finish (counted with an atomic, after a release fence) merges the
-// group's partials in split order.  Both kinds share the 8-wave shape.
+// group's partials in split order.  Both kinds use 8 waves and a 2048-sample
+// stage: CMP tiles with 2 parameters per wave, CRS tiles with 4 (the
+// exhaustive scan's tile shape 4, whose per-trace loop work is shared by 4
+// parameters); both keep their windows behind a branch.  The stage and
+// 128-trace metadata parts keep the LDS union at two workgroups per CU.
 // ---------------------------------------------------------------------------
 constexpr int BATCH_NW = 8;
 constexpr int BATCH_P_CMP = 2;
-constexpr int BATCH_P_CRS = 2;
-constexpr int BATCH_CAP = 3072;
-constexpr int BATCH_TMAX = 256;
+constexpr int BATCH_P_CRS = 4;
+constexpr int BATCH_CAP = 2048;
+constexpr int BATCH_TMAX = 128;
 
 __global__ void reset_counters_kernel(unsigned int *c, int n)
 {
@@ -135,7 +139,7 @@ batch_kernel(BatchArgs b)
             scan_tile<SEMB_KIND_CMP, WC, BATCH_P_CMP, BATCH_NW, BATCH_CAP, BATCH_TMAX, true>(
                 b.g, b.j, b.pc, L.c, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, nullptr, bS, bI, bSt);
         else
-            scan_tile<SEMB_KIND_CRS, WR, BATCH_P_CRS, BATCH_NW, BATCH_CAP, BATCH_TMAX, false>(
+            scan_tile<SEMB_KIND_CRS, WR, BATCH_P_CRS, BATCH_NW, BATCH_CAP, BATCH_TMAX, true>(
                 b.g, b.j, b.pr, L.r, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, nullptr, bS, bI, bSt);
         const int64_t row = b.j.out_off[tl.job] + tl.sblk * WAVE + lane;
         if (tl.nsplit <= 1) {

@@ -166,6 +166,19 @@ def test_batch_plan_host_only(semb):
     assert tiles[0][0] in (1, 2)
 
 
+def test_batch_plan_rounds_the_split_to_whole_blocks(semb):
+    """A requested split is rounded up to whole 32-parameter blocks (8 waves x
+    4 parameters of a CRS tile)."""
+    import numpy as np
+    kind = np.array([1, 0], np.int32)
+    tiles, ng, npart = semb.batch_plan(kind, np.array([0, 1], np.int32), np.array([0, 2, 3], np.int32),
+                                       np.array([0, 1, 1], np.int32), np.array([64, 64], np.int32),
+                                       np.array([0, 3, 6], np.int32), 101, 2541, 40)
+    spans = sorted((int(t[2]), int(t[3])) for t in tiles if t[0] == 0)
+    assert spans[0] == (0, 64) and spans[-1] == (2496, 2541)
+    assert all(b - a == 64 for a, b in spans[:-1]) and len(spans) == 40
+
+
 def test_batch_plan_rejects_bad_input(semb):
     import numpy as np
     with pytest.raises(semb.SembError):
