@@ -307,7 +307,7 @@ semb_status scan_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_
  * per (kind, w, traces per job, samples per trace), the two sizes rounded up
  * to powers of two from the host fields ntraces / ngathers (times max_apert
  * for CRS) and ns_max; without an entry the kind's default is used (shape 0
- * for CMP, 1 for CRS).  The table is process-wide and guarded by a mutex.
+ * for CMP, 2 for CRS).  The table is process-wide and guarded by a mutex.
  * Tuned tile shapes are the counterpart of the paper's tuning of its tile and
  * prefetch sizes to the local store (section 3.3, Eq. (2)).
  * ------------------------------------------------------------------------- */

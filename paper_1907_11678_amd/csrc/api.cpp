@@ -188,7 +188,7 @@ ShapeKey shape_key(int kind, int w, const semb_gathers *g, const semb_jobs *jobs
     return ShapeKey{kind, w, log2_bucket(fold * apert), log2_bucket(g->ns_max)};
 }
 
-int default_shape(int kind) { return kind == SEMB_KIND_CRS ? 1 : 0; }
+int default_shape(int kind) { return kind == SEMB_KIND_CRS ? 2 : 0; }
 
 int chosen_shape(int kind, int w, const semb_gathers *g, const semb_jobs *jobs)
 {
@@ -200,7 +200,7 @@ int chosen_shape(int kind, int w, const semb_gathers *g, const semb_jobs *jobs)
 const char *const kShapeNames[semb::kScanShapes] = {
     "4 waves x 4 parameters (2 for w > 15), 2048-sample stage, windows behind a branch",
     "8 waves x 2 parameters, 3072-sample stage, branch-free windows",
-    "8 waves x 2 parameters, 3072-sample stage, windows behind a branch",
+    "8 waves x 4 parameters (2 for w > 15), 2560-sample stage, branch-free windows",
     "4 waves x 4 parameters (2 for w > 15), 2048-sample stage, branch-free windows",
     "8 waves x 4 parameters (2 for w > 15), 2048-sample stage, windows behind a branch",
     "16 waves x 4 parameters (2 for w > 15), 2048-sample stage, windows behind a branch",
@@ -301,7 +301,7 @@ semb_status point_common(bool grad, const semb_gathers *g, const semb_jobs *jobs
     return hip_status(timed(stream, [&] { return semb::launch_point(kind, a, stream); }), "stack launch");
 }
 
-constexpr int kBatchBlock = 32;  // parameters per CRS block of the batch kernel (8 waves x 4)
+constexpr int kBatchBlock = 32;  // parameters per CRS block of the batch kernel (8 waves x 4 for w <= 9)
 
 bool batch_w_ok(int w) { return w == 9 || w == 11 || w == 15; }
 

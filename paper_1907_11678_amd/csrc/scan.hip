@@ -95,14 +95,16 @@ hipError_t launch_energy_w(const float *samples, const int64_t *sample_off, cons
 // outputs; otherwise it stores a partial pick, and the last tile of its group
 // to finish (counted with an atomic, after a release fence) merges the
 // group's partials in split order.  Both kinds use 8 waves and a 2048-sample
-// stage: CMP tiles with 2 parameters per wave, CRS tiles with 4 (the
-// exhaustive scan's tile shape 4, whose per-trace loop work is shared by 4
-// parameters); both keep their windows behind a branch.  The stage and
-// 128-trace metadata parts keep the LDS union at two workgroups per CU.
+// stage: CMP tiles with 2 parameters per wave, CRS tiles with 4 for windows
+// up to 9 samples (each trace's loop work is then shared by 4 parameters) and
+// 2 for longer ones, whose 4 x (w + 2) accumulators would not fit the
+// 128-VGPR budget of 4 waves per SIMD; both keep their windows behind a
+// branch.  The stage and 128-trace metadata parts keep the LDS union at two
+// workgroups per CU.
 // ---------------------------------------------------------------------------
 constexpr int BATCH_NW = 8;
 constexpr int BATCH_P_CMP = 2;
-constexpr int BATCH_P_CRS = 4;
+constexpr int batch_p_crs(int wr) { return wr <= 9 ? 4 : 2; }
 constexpr int BATCH_CAP = 2048;
 constexpr int BATCH_TMAX = 128;
 
@@ -116,7 +118,7 @@ __global__ void __launch_bounds__(BATCH_NW * WAVE) __attribute__((amdgpu_waves_p
 batch_kernel(BatchArgs b)
 {
     using LC = StageLds<SEMB_KIND_CMP, WC, BATCH_P_CMP, BATCH_NW, BATCH_CAP, BATCH_TMAX>;
-    using LR = StageLds<SEMB_KIND_CRS, WR, BATCH_P_CRS, BATCH_NW, BATCH_CAP, BATCH_TMAX>;
+    using LR = StageLds<SEMB_KIND_CRS, WR, batch_p_crs(WR), BATCH_NW, BATCH_CAP, BATCH_TMAX>;
     __shared__ union U {
         LC c;
         LR r;
@@ -139,7 +141,7 @@ batch_kernel(BatchArgs b)
             scan_tile<SEMB_KIND_CMP, WC, BATCH_P_CMP, BATCH_NW, BATCH_CAP, BATCH_TMAX, true>(
                 b.g, b.j, b.pc, L.c, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, nullptr, bS, bI, bSt);
         else
-            scan_tile<SEMB_KIND_CRS, WR, BATCH_P_CRS, BATCH_NW, BATCH_CAP, BATCH_TMAX, true>(
+            scan_tile<SEMB_KIND_CRS, WR, batch_p_crs(WR), BATCH_NW, BATCH_CAP, BATCH_TMAX, true>(
                 b.g, b.j, b.pr, L.r, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, nullptr, bS, bI, bSt);
         const int64_t row = b.j.out_off[tl.job] + tl.sblk * WAVE + lane;
         if (tl.nsplit <= 1) {

@@ -521,10 +521,11 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
 //   0: 4 waves x 4 parameters per lane (2 for w > 15) at <= 128 VGPRs (4 waves
 //      per SIMD), 2048-position stage, windows behind a branch -- the CMP
 //      default;
-//   1: 8 waves x 2 parameters, 3072-position stage, branch-free windows --
-//      the CRS default (its per-evaluation table read and wider apertures
-//      favour occupancy);
-//   2: 8 waves x 2 parameters, 3072-position stage, windows behind a branch;
+//   1: 8 waves x 2 parameters, 3072-position stage, branch-free windows;
+//   2: 8 waves x 4 parameters (2 for w > 15), 2560-position stage,
+//      branch-free windows -- the CRS default: 4 parameters share each
+//      trace's loop work, the loads of all 4 windows are in flight together,
+//      and the stage still leaves two workgroups per CU;
 //   3: 4 waves x 4 parameters (2 for w > 15), 2048-position stage,
 //      branch-free windows;
 //   4: 8 waves x 4 parameters (2 for w > 15), 2048-position stage, windows
@@ -546,8 +547,8 @@ struct ShapeT<1, W> {
 };
 template <int W>
 struct ShapeT<2, W> {
-    static constexpr int NW = 8, P = 2, CAP = 3072, TMAX = 256, WPE = 1;
-    static constexpr bool BRANCHY = true;
+    static constexpr int NW = 8, P = W <= 15 ? 4 : 2, CAP = 2560, TMAX = 128, WPE = 2;
+    static constexpr bool BRANCHY = false;
 };
 template <int W>
 struct ShapeT<3, W> {

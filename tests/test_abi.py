@@ -198,16 +198,16 @@ def test_shape_names_and_host_side_table(semb):
     j = _jobs(semb, max_apert=9)
     L.semb_clear_tuning()
     assert L.semb_scan_shape(0, 11, C.byref(g), C.byref(j)) == 0
-    assert L.semb_scan_shape(1, 11, C.byref(g), C.byref(j)) == 1
+    assert L.semb_scan_shape(1, 11, C.byref(g), C.byref(j)) == 2   # the CRS default
     assert L.semb_set_scan_shape(1, 11, C.byref(g), C.byref(j), 3) == 0
     assert L.semb_scan_shape(1, 11, C.byref(g), C.byref(j)) == 3
     g2 = _gathers(semb, ntraces=600, ngathers=20, ns_max=1900)  # another ns bucket
-    assert L.semb_scan_shape(1, 11, C.byref(g2), C.byref(j)) == 1
-    assert L.semb_scan_shape(1, 9, C.byref(g), C.byref(j)) == 1   # other window
+    assert L.semb_scan_shape(1, 11, C.byref(g2), C.byref(j)) == 2
+    assert L.semb_scan_shape(1, 9, C.byref(g), C.byref(j)) == 2   # other window
     assert L.semb_set_scan_shape(1, 11, C.byref(g), C.byref(j), semb.SCAN_SHAPES) == 1
     assert L.semb_set_scan_shape(2, 11, C.byref(g), C.byref(j), 0) == 1
     assert L.semb_set_scan_shape(1, 11, C.byref(g), C.byref(j), -1) == 0
-    assert L.semb_scan_shape(1, 11, C.byref(g), C.byref(j)) == 1
+    assert L.semb_scan_shape(1, 11, C.byref(g), C.byref(j)) == 2
     L.semb_clear_tuning()
 
 

@@ -73,13 +73,16 @@ def _kind_rows(bw, kind):
     return np.concatenate(rows) if rows else np.zeros(0, np.int64)
 
 
-@pytest.mark.parametrize("split", [256, 4096])
-def test_batch_equals_per_kind_scans(split):
+@pytest.mark.parametrize("split,w_cmp,w_crs", [(256, 11, 9), (4096, 11, 9), (256, 15, 15), (256, 9, 11)])
+def test_batch_equals_per_kind_scans(split, w_cmp, w_crs):
     """A 40-gather stretch of the batched line (uneven fold 8..120 and length
     500..2000): the batch must reproduce cmp_scan on its CMP jobs and crs_scan
-    on its CRS jobs exactly (same per-cell sums in the same order)."""
+    on its CRS jobs exactly (same per-cell sums in the same order), for every
+    window the batch kernel is built for (CRS tiles hold 4 parameters per wave
+    at w 9 and 2 above)."""
+    import dataclasses
     import torch
-    bw = synth.batched_line(ids=range(2000, 2040))
+    bw = dataclasses.replace(synth.batched_line(ids=range(2000, 2040)), w_cmp=w_cmp, w_crs=w_crs)
     b = Batch(bw, split)
     b.run()
     torch.cuda.synchronize()

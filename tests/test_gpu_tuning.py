@@ -66,7 +66,7 @@ def test_every_shape_equals_the_default(kind, w):
         semb.set_scan_shape(KIND[kind], w, dg, dj, -1)
 
 
-@pytest.mark.parametrize("kind,shape", [("cmp", 1), ("cmp", 3), ("crs", 0), ("crs", 2)])
+@pytest.mark.parametrize("kind,shape", [("cmp", 1), ("cmp", 3), ("crs", 0), ("crs", 1), ("crs", 4)])
 def test_non_default_shape_matches_oracle(kind, shape):
     import paper_1907_11678_amd as semb
     if kind == "cmp":
