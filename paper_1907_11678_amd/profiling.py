@@ -191,6 +191,18 @@ def write_record(rec: dict, path: str, header: str = ""):
             f.write(f"{k}: {v}\n")
 
 
+def comment_header(path: str) -> str:
+    """The leading '#' lines of an existing record (kept when it is rewritten)."""
+    if not os.path.exists(path):
+        return ""
+    out = []
+    for line in open(path):
+        if not line.startswith("#"):
+            break
+        out.append(line.rstrip("\n"))
+    return "\n".join(out)
+
+
 def read_record(path: str) -> dict | None:
     if not os.path.exists(path):
         return None
@@ -221,7 +233,7 @@ def main(argv):
         print(json.dumps(counter_summary(argv[3:], argv[1], int(float(argv[2]))), indent=1))
     elif len(argv) == 6 and argv[0] == "traffic":
         rec = traffic_record(argv[1], argv[2], argv[3], int(argv[4]))
-        write_record(rec, argv[5])
+        write_record(rec, argv[5], header=comment_header(argv[5]))
         print("\n".join(f"{k}: {v}" for k, v in rec.items()))
     else:
         print(__doc__)

@@ -49,6 +49,13 @@ def test_record_round_trip_and_digest_check(tmp_path, monkeypatch):
     assert profiling.current_traffic(str(tmp_path / "missing.txt")) is None
 
 
+def test_rewriting_a_record_keeps_its_comment_header(tmp_path):
+    p = str(tmp_path / "rec.txt")
+    profiling.write_record({"traffic_bytes_per_launch": 1.0}, p, header="# line one\n#\n# line three")
+    assert profiling.comment_header(p) == "# line one\n#\n# line three"
+    assert profiling.comment_header(str(tmp_path / "none.txt")) == ""
+
+
 def test_counter_summary_averages_full_launches_over_passes(tmp_path):
     evals = 64 * 1000  # 1000 64-lane evaluations per launch
     p1 = _counters(tmp_path / "p1.csv", [
