@@ -200,7 +200,7 @@ int chosen_shape(int kind, int w, const semb_gathers *g, const semb_jobs *jobs)
 const char *const kShapeNames[semb::kScanShapes] = {
     "4 waves x 4 parameters (2 for w > 15), 2048-sample stage, windows behind a branch",
     "8 waves x 2 parameters, 3072-sample stage, branch-free windows",
-    "8 waves x 4 parameters (2 for w > 15), 2560-sample stage, branch-free windows",
+    "8 waves x 4 parameters (2 for w > 9), 2560-sample stage, branch-free windows",
     "4 waves x 4 parameters (2 for w > 15), 2048-sample stage, branch-free windows",
     "8 waves x 4 parameters (2 for w > 15), 2048-sample stage, windows behind a branch",
     "16 waves x 4 parameters (2 for w > 15), 2048-sample stage, windows behind a branch",

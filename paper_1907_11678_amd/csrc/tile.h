@@ -61,6 +61,16 @@ __device__ __forceinline__ void lds_dma(const float *g, float *lds_base)
     __builtin_amdgcn_global_load_lds((void *)g, (lds_void *)lds_base, 4, 0, 0);
 }
 
+// Stage position id of a tile's LDS stage as one address that the optimiser
+// cannot re-derive, so the window's w + 1 samples and its three energy words
+// are all read from this address plus immediate offsets.
+__device__ __forceinline__ const float *stage_at(const float *stage, int id)
+{
+    unsigned byte = (unsigned)id * 4u;
+    asm("" : "+v"(byte));
+    return reinterpret_cast<const float *>(reinterpret_cast<const char *>(stage) + byte);
+}
+
 // A wave-uniform double moved into scalar registers (frees two VGPRs).
 __device__ __forceinline__ double to_sgpr(double v)
 {
@@ -115,20 +125,28 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk)
 // LDS once per tile when the aperture has at most TMAX traces, else once per
 // TMAX-trace part of it.
 // ---------------------------------------------------------------------------
+// What the hot loop needs of one trace, read with one LDS load (all 16 bytes
+// for CMP; CRS takes its traveltime terms from the parameter table and reads
+// the first 8): the last valid window start (-1: nothing staged), the LDS
+// position of the trace's sample 0 in its stage, and h^2/dt^2.
+struct __align__(16) TraceRun {
+    int lim;
+    int off;
+    double cc;
+};
+
 template <int KIND, int W, int P, int NW, int CAP, int TMAX>
 struct StageLds {
-    float lf[CAP];                                  // staged samples
-    float lu0[CAP], lu1[CAP], lu2[CAP];             // their window energy (Gram form)
+    float st[4][CAP];                               // staged samples, then their window energy
+                                                    // (Gram form): u0, u1, u2^2
     double2 tab[KIND == SEMB_KIND_CRS ? NW * P : 1][WAVE];  // CRS: (2 alpha + beta, alpha^2 + gamma)
     // the traces of the current part: fixed per tile ...
     long long t_base[TMAX];                         // element of the trace's sample 0
-    double t_cc[TMAX];                              // h^2/dt^2
     int t_ns[TMAX];
     float t_dm[TMAX];                               // midpoint displacement (CRS)
     // ... and per parameter block
     int t_lo[TMAX], t_len[TMAX];                    // staged range [lo, lo + len)
-    int t_lim[TMAX];                                // last valid window start, -1: nothing staged
-    int t_off[TMAX];                                // LDS position of sample 0 in its chunk
+    TraceRun run[TMAX];                             // what the hot loop reads per trace
     double pq[NW * P], pA[NW * P], pB[NW * P];      // the current parameter block
     double box[6];                                  // its bounds: q, A, B (lo, hi)
     int ag_s[SEMB_APERT_LIMIT];
@@ -151,7 +169,7 @@ __device__ __forceinline__ void load_traces(const GatherView &g, LDS &L, int na,
         L.t_base[e] = g.sample_off[gg] + (long long)li * nsg;
         L.t_ns[e] = nsg;
         const double h = g.half_offset[i];
-        L.t_cc[e] = h * h * inv_dt * inv_dt;
+        L.run[e].cc = h * h * inv_dt * inv_dt;
         // the displacement as the kernels use it: rounded to FP32
         L.t_dm[e] = KIND == SEMB_KIND_CRS ? (float)((double)g.midpoint[i] - xc) : 0.f;
     }
@@ -276,7 +294,7 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
             {
                 const double qlo = L.box[0], qhi = L.box[1];
                 for (int e = tid; e < nt; e += NTH) {
-                    const double cc = L.t_cc[e];
+                    const double cc = L.run[e].cc;
                     const int nsg = L.t_ns[e];
                     int len = 0, lo = 0;
                     double Tlo, Thi;
@@ -312,7 +330,7 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                     L.t_lo[e] = lo;
                     L.t_len[e] = len;
                     // a trace without staged samples gets lim = -1: none of its windows count
-                    L.t_lim[e] = len > 0 ? nsg - 1 - W : -1;
+                    L.run[e].lim = len > 0 ? nsg - 1 - W : -1;
                 }
             }
             __syncthreads();
@@ -336,7 +354,7 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                     len = min(len, CAP);
                     incl = len;
                 }
-                if (wv == 0 && lane < nfit) L.t_off[e] = incl - len - L.t_lo[e];
+                if (wv == 0 && lane < nfit) L.run[e].off = incl - len - L.t_lo[e];
 
                 // ---- stage the samples and their window energy -------------------
                 // Direct global->LDS loads (global_load_lds_dword): lane l of a wave
@@ -350,10 +368,10 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                     for (int p0 = 0; p0 < rl; p0 += WAVE) {
                         if (p0 + lane < rl) {
                             const long long gi = src + p0 + lane;
-                            lds_dma(g.samples + gi, &L.lf[rb + p0]);
-                            lds_dma(pv.u0 + gi, &L.lu0[rb + p0]);
-                            lds_dma(pv.u1 + gi, &L.lu1[rb + p0]);
-                            lds_dma(pv.u2sq + gi, &L.lu2[rb + p0]);
+                            lds_dma(g.samples + gi, &L.st[0][rb + p0]);
+                            lds_dma(pv.u0 + gi, &L.st[1][rb + p0]);
+                            lds_dma(pv.u1 + gi, &L.st[2][rb + p0]);
+                            lds_dma(pv.u2sq + gi, &L.st[3][rb + p0]);
                         }
                     }
                 }
@@ -365,7 +383,7 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                             const double dmr = L.t_dm[e];
                             const double al = L.pA[pl] * 2.0 * dmr * inv_dt;
                             const double be = L.pB[pl] * 2.0 * dmr * dmr * inv_dt;
-                            L.tab[pl][lane] = make_double2(2.0 * al + be, fma(al, al, L.pq[pl] * L.t_cc[e]));
+                            L.tab[pl][lane] = make_double2(2.0 * al + be, fma(al, al, L.pq[pl] * L.run[e].cc));
                         }
                     }
                 }
@@ -380,10 +398,26 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                 for (int p = 0; p < P; ++p) qd[p] = to_sgpr(L.pq[wv * P + p]);
                 if (lane_on) {
                     for (int r = 0; r < nfit; ++r) {
-                        const int lim = L.t_lim[cb + r];
+                        // one LDS load per trace: lim and off, and for CMP cc (the
+                        // empty asm keeps the optimiser from splitting the load
+                        // around the test below)
+                        int lim, off;
+                        double cc = 0.0;
+                        if (CRS) {
+                            typedef int v2i __attribute__((ext_vector_type(2)));
+                            v2i tr = *reinterpret_cast<const v2i *>(&L.run[cb + r]);
+                            asm("" : "+v"(tr));
+                            lim = tr.x;
+                            off = tr.y;
+                        } else {
+                            typedef int v4i __attribute__((ext_vector_type(4)));
+                            v4i tr = *reinterpret_cast<const v4i *>(&L.run[cb + r]);
+                            asm("" : "+v"(tr));
+                            lim = tr.x;
+                            off = tr.y;
+                            cc = __hiloint2double(tr.w, tr.z);
+                        }
                         if (lim < 0) continue;  // uniform: no staged window on this trace
-                        const int off = L.t_off[cb + r];
-                        const double cc = L.t_cc[cb + r];
                         if (BRANCHY) {
 #pragma unroll
                             for (int p = 0; p < P; ++p) {
@@ -404,16 +438,17 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                                 const float x = (float)__builtin_amdgcn_fract(tau);
                                 const float u = 1.f - x;
                                 const int id = a + off;
+                                const float *sp = stage_at(&L.st[0][0], id);
                                 float fw[W + 1];
 #pragma unroll
-                                for (int j = 0; j <= W; ++j) fw[j] = L.lf[id + j];
+                                for (int j = 0; j <= W; ++j) fw[j] = sp[j];
 #pragma unroll
                                 for (int j = 0; j < W; ++j) {
                                     U[p][j] = fmaf(u, fw[j], U[p][j]);
                                     U[p][j] = fmaf(x, fw[j + 1], U[p][j]);
                                 }
-                                const float tq = fmaf(x, L.lu1[id], L.lu0[id]);
-                                D[p] += fmaf(tq, tq, L.lu2[id]);
+                                const float tq = fmaf(x, sp[2 * CAP], sp[CAP]);
+                                D[p] += fmaf(tq, tq, sp[3 * CAP]);
                                 Mc[p] += 1.f;
                             }
                         } else {
@@ -444,14 +479,14 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                                 const int id = idx[p];
                                 float fw[W + 1];
 #pragma unroll
-                                for (int j = 0; j <= W; ++j) fw[j] = L.lf[id + j];
+                                for (int j = 0; j <= W; ++j) fw[j] = L.st[0][id + j];
 #pragma unroll
                                 for (int j = 0; j < W; ++j) {
                                     U[p][j] = fmaf(uw[p], fw[j], U[p][j]);
                                     U[p][j] = fmaf(xw[p], fw[j + 1], U[p][j]);
                                 }
-                                const float tq = fmaf(xw[p], L.lu1[id], L.lu0[id]);
-                                D[p] = fmaf(vm[p], fmaf(tq, tq, L.lu2[id]), D[p]);
+                                const float tq = fmaf(xw[p], L.st[2][id], L.st[1][id]);
+                                D[p] = fmaf(vm[p], fmaf(tq, tq, L.st[3][id]), D[p]);
                                 Mc[p] += vm[p];
                             }
                         }
@@ -490,9 +525,9 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
     }
 
     // ---- pick across the waves (largest S, then smallest index) --------------
-    float *rS = L.lf;  // reuse the stage buffers
-    int *rI = reinterpret_cast<int *>(L.lu0);
-    float *rT = L.lu1;
+    float *rS = L.st[0];  // reuse the stage buffers
+    int *rI = reinterpret_cast<int *>(L.st[1]);
+    float *rT = L.st[2];
     __syncthreads();
     rS[wv * WAVE + lane] = bS;
     rI[wv * WAVE + lane] = bI;
@@ -522,10 +557,10 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
 //      per SIMD), 2048-position stage, windows behind a branch -- the CMP
 //      default;
 //   1: 8 waves x 2 parameters, 3072-position stage, branch-free windows;
-//   2: 8 waves x 4 parameters (2 for w > 15), 2560-position stage,
+//   2: 8 waves x 4 parameters (2 for w > 9), 2560-position stage,
 //      branch-free windows -- the CRS default: 4 parameters share each
 //      trace's loop work, the loads of all 4 windows are in flight together,
-//      and the stage still leaves two workgroups per CU;
+//      and the stage and 128 VGPRs still leave two workgroups per CU;
 //   3: 4 waves x 4 parameters (2 for w > 15), 2048-position stage,
 //      branch-free windows;
 //   4: 8 waves x 4 parameters (2 for w > 15), 2048-position stage, windows
@@ -547,7 +582,7 @@ struct ShapeT<1, W> {
 };
 template <int W>
 struct ShapeT<2, W> {
-    static constexpr int NW = 8, P = W <= 15 ? 4 : 2, CAP = 2560, TMAX = 128, WPE = 2;
+    static constexpr int NW = 8, P = W <= 9 ? 4 : 2, CAP = 2560, TMAX = 128, WPE = 2;
     static constexpr bool BRANCHY = false;
 };
 template <int W>
