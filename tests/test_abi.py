@@ -132,6 +132,82 @@ def test_point_calls_validate(semb):
     assert L.semblance_grad(C.byref(g), C.byref(j), 1, P, P, 10, P, None, None) == 1    # even w
 
 
+def test_refinement_peaks_best_of_and_corrected_gathers_validate(semb):
+    """Host-side checks of the point-path helpers: each bad argument is
+    rejected with SEMB_EINVAL before anything touches the (fake) device
+    pointers."""
+    L = semb.lib()
+    g = _gathers(semb)
+    j = _jobs(semb)
+    P = C.c_void_p(0x4000)
+
+    def opts(**kw):
+        o = semb.CRefineOpts(8, 0.5, 1.25, (C.c_float * 3)(1e-4, 1e-8, 1e-7), (C.c_float * 3)(-1, -1, 0),
+                             (C.c_float * 3)(1, 1, 1))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    assert L.semb_refine(C.byref(g), C.byref(j), 7, P, C.byref(opts()), 11, P, P, None) == 1   # kind
+    assert L.semb_refine(C.byref(g), C.byref(j), 0, P, None, 11, P, P, None) == 1             # no options
+    for bad in (dict(steps=-1), dict(grow=0.5), dict(eta0=float("nan")), dict(eta0=-1.0),
+                dict(lo=(C.c_float * 3)(0, 0, 2)), dict(scale=(C.c_float * 3)(1, float("inf"), 1))):
+        assert L.semb_refine(C.byref(g), C.byref(j), 0, P, C.byref(opts(**bad)), 11, P, P, None) == 1, bad
+    assert L.semb_refine(C.byref(g), C.byref(j), 0, None, C.byref(opts()), 11, P, P, None) == 1  # no theta
+
+    assert L.semb_theta_from_best(P, -1, None, 0, None, 0, P, 4, P, None) == 1                # n_out
+    assert L.semb_theta_from_best(P, 10, None, 0, None, 0, None, 4, P, None) == 1             # no q
+    assert L.semb_theta_from_best(P, 10, None, 0, None, 0, P, 0, P, None) == 1                # nq
+    assert L.semb_theta_from_best(P, 10, P, 0, P, 2, P, 4, P, None) == 1                      # nA with A
+
+    assert L.semb_corrected_gathers(C.byref(g), C.byref(j), 5, P, P, P, None) == 1            # kind
+    assert L.semb_corrected_gathers(C.byref(g), C.byref(j), 0, None, P, P, None) == 1         # no theta
+    assert L.semb_corrected_gathers(C.byref(g), C.byref(j), 0, P, None, P, None) == 1         # no offsets
+
+    for n, nA, nB, nq, K in ((-1, 1, 1, 5, 2), (4, 0, 1, 5, 2), (4, 1, 1, 0, 2), (4, 1, 1, 5, 0),
+                             (4, 1, 1, 5, 9), (4, 70000, 70000, 5, 2)):
+        assert L.semb_panel_peaks(P, n, nA, nB, nq, K, P, P, None) == 1, (n, nA, nB, nq, K)
+    assert L.semb_panel_peaks(None, 4, 1, 1, 5, 2, P, P, None) == 1
+
+    assert L.semb_best_of(0, 4, P, P, P, P, P, P, None) == 1
+    assert L.semb_best_of(2, -1, P, P, P, P, P, P, None) == 1
+    assert L.semb_best_of(2, 4, P, None, P, P, P, P, None) == 1
+    assert semb.last_error()
+
+
+def test_scan_batch_validates(semb):
+    L = semb.lib()
+    g = _gathers(semb, nsamples=1000)
+    j = _jobs(semb)
+    P = C.c_void_p(0x4000)
+
+    def batch(**kw):
+        b = semb.CBatch(P, P, 101, 11, P, 11, P, 11, P, 21, 9)
+        for k, v in kw.items():
+            setattr(b, k, v)
+        return b
+
+    need = semb.batch_workspace_bytes(1000, 11, 9, 0, 0)
+    ws = C.c_void_p(0x100000)
+    out = _outs(semb)
+    tiles = C.c_void_p(0x5000)
+    assert L.scan_batch(C.byref(g), C.byref(j), C.byref(batch(w_cmp=13)), tiles, 1, 0, 0, C.byref(out), ws, need,
+                        None) == 1                                                           # window
+    assert L.scan_batch(C.byref(g), C.byref(j), C.byref(batch(nq_cmp=0)), tiles, 1, 0, 0, C.byref(out), ws, need,
+                        None) == 1                                                           # no CMP grid
+    assert L.scan_batch(C.byref(g), C.byref(j), C.byref(batch()), tiles, -1, 0, 0, C.byref(out), ws, need,
+                        None) == 1                                                           # plan sizes
+    assert L.scan_batch(C.byref(g), C.byref(j), C.byref(batch()), None, 4, 0, 0, C.byref(out), ws, need,
+                        None) == 1                                                           # no tiles
+    with_panel = semb.COutputs(0x3000, 0x3000, 0x3000, 0x3000, None)
+    assert L.scan_batch(C.byref(g), C.byref(j), C.byref(batch()), tiles, 1, 0, 0, C.byref(with_panel), ws, need,
+                        None) == 1                                                           # panel
+    assert L.scan_batch(C.byref(g), C.byref(j), C.byref(batch()), tiles, 1, 0, 0, C.byref(out), ws, need - 1,
+                        None) == 2                                                           # workspace size
+    assert L.scan_batch(C.byref(g), C.byref(j), C.byref(batch()), tiles, 1, 0, 0, C.byref(out),
+                        C.c_void_p(0x100004), need, None) == 2                               # alignment
+
+
 def test_version(semb):
     assert "gfx950" in semb.version()
 
