@@ -294,7 +294,10 @@ size_t semb_batch_workspace_bytes(int64_t nsamples, int32_t w_cmp, int32_t w_crs
  * scans (panel must be NULL); best indexes the job's own grid.  The workspace
  * holds the window-energy planes, the tile and group counters (reset by a
  * kernel on `stream`, so the call can be captured in a HIP graph and
- * replayed) and the partial picks.  Calls that overlap on one workspace race. */
+ * replayed) and the partial picks.  Calls that overlap on one workspace race.
+ * ngroups and nparts must be the plan's; a device tile that no such plan
+ * could hold (job, sample block, parameter range, group or partial slot out
+ * of range) is skipped and leaves its rows unwritten. */
 semb_status scan_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_batch *b,
                        const semb_tile *tiles, int64_t ntiles, int32_t ngroups, int32_t nparts,
                        const semb_outputs *out, void *ws, size_t ws_bytes, hipStream_t stream);

@@ -338,13 +338,15 @@ int64_t semb_batch_plan(const semb_batch_host *h, int32_t split_params, semb_til
         fail(SEMB_EINVAL, "semb_batch_plan: invalid sizes");
         return -1;
     }
-    const int32_t split = (split_params + kBatchBlock - 1) / kBatchBlock * kBatchBlock;
+    // whole blocks, in 64-bit so that a split of INT32_MAX ("never split") cannot overflow
+    const int64_t split64 = ((int64_t)split_params + kBatchBlock - 1) / kBatchBlock * kBatchBlock;
+    const int32_t split = (int32_t)std::min<int64_t>(split64, 0x7fffffffLL);
     struct Item {
         double cost;
         semb_tile t;
     };
     std::vector<Item> items;
-    int32_t ng = 0, np = 0;
+    int64_t ng = 0, np = 0;
     for (int32_t j = 0; j < h->njobs; ++j) {
         const int32_t c = h->central[j];
         if (c < 0 || c >= h->ngathers) {
@@ -370,13 +372,18 @@ int64_t semb_batch_plan(const semb_batch_host *h, int32_t split_params, semb_til
             ntr = h->trace_ptr[c + 1] - h->trace_ptr[c];
         }
         const int32_t npar = crs ? h->npar_crs : h->npar_cmp;
-        const int32_t nsplit = (npar + split - 1) / split;
+        const int32_t nsplit = (int32_t)(((int64_t)npar + split - 1) / split);
         const int32_t nsb = (h->ns[c] + 63) / 64;
         for (int32_t b = 0; b < nsb; ++b) {
             const int32_t nrow = std::min(64, h->ns[c] - 64 * b);
-            const int32_t grp = nsplit > 1 ? ng++ : -1;
-            const int32_t base = nsplit > 1 ? np : 0;
+            const int32_t grp = nsplit > 1 ? (int32_t)ng++ : -1;
+            const int32_t base = nsplit > 1 ? (int32_t)np : 0;
             if (nsplit > 1) np += nsplit;
+            // groups and partial slots index 32-bit fields and a workspace of np * 64 partials
+            if (ng > 0x7fffffffLL || np > 0x7fffffffLL / 64) {
+                fail(SEMB_EINVAL, "semb_batch_plan: too many split tiles; use a larger split_params");
+                return -1;
+            }
             for (int32_t sp = 0; sp < nsplit; ++sp) {
                 Item it;
                 it.t.job = j;
@@ -395,8 +402,8 @@ int64_t semb_batch_plan(const semb_batch_host *h, int32_t split_params, semb_til
     }
     // longest first; ties keep job order
     std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
-    if (ngroups) *ngroups = ng;
-    if (nparts) *nparts = np;
+    if (ngroups) *ngroups = (int32_t)ng;
+    if (nparts) *nparts = (int32_t)np;
     if (tiles) {
         if ((int64_t)items.size() > max_tiles) {
             fail(SEMB_EINVAL, "semb_batch_plan: %zu tiles do not fit in max_tiles = %lld", items.size(),
@@ -478,6 +485,8 @@ semb_status scan_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_
     a.ntiles = ntiles;
     a.counters = reinterpret_cast<unsigned int *>(base + lay.counters);
     a.partials = reinterpret_cast<semb::Partial *>(base + lay.partials);
+    a.ngroups = ngroups;
+    a.nparts = nparts;
     a.best = out->best;
     a.s_best = out->s_best;
     a.stack = out->stack;

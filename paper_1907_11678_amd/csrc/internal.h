@@ -75,6 +75,7 @@ struct BatchArgs {
     int64_t ntiles;
     unsigned int *counters;   // [1 + ngroups]: tile counter, then finished splits per group
     Partial *partials;        // [nparts * 64]
+    int32_t ngroups, nparts;  // the plan's sizes; a tile outside them is skipped
     int32_t *best;
     float *s_best;
     float *stack;

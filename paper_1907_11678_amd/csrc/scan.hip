@@ -134,7 +134,16 @@ batch_kernel(BatchArgs b)
         const long long t = sh_tile;
         if (t >= b.ntiles) break;  // uniform: every workgroup leaves once the list is drained
         const semb_tile tl = b.tiles[t];
+        // A tile that no plan of these jobs and sizes could contain is skipped
+        // (its rows stay unwritten) rather than read or write out of bounds.
+        if (tl.job < 0 || tl.job >= b.j.njobs || tl.sblk < 0 || tl.sblk >= b.j.n_sblk) continue;
         const int kind = b.kind[tl.job];
+        if (kind != SEMB_KIND_CMP && kind != SEMB_KIND_CRS) continue;
+        if (tl.p_begin < 0 || tl.p_begin >= tl.p_end || tl.p_end > (kind == SEMB_KIND_CMP ? b.pc.npar : b.pr.npar))
+            continue;
+        if (tl.nsplit > 1 && (tl.group < 0 || tl.group >= b.ngroups || tl.split < 0 || tl.split >= tl.nsplit ||
+                              tl.part_base < 0 || (int64_t)tl.part_base + tl.nsplit > b.nparts))
+            continue;
         float bS, bSt;
         int bI;
         if (kind == SEMB_KIND_CMP)

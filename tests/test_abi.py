@@ -255,6 +255,16 @@ def test_batch_plan_rounds_the_split_to_whole_blocks(semb):
     assert all(b - a == 64 for a, b in spans[:-1]) and len(spans) == 40
 
 
+def test_batch_plan_never_splits_at_int32_max(semb):
+    import numpy as np
+    kind = np.array([1, 0], np.int32)
+    tiles, ng, npart = semb.batch_plan(kind, np.array([0, 1], np.int32), np.array([0, 2, 3], np.int32),
+                                       np.array([0, 1, 1], np.int32), np.array([130, 64], np.int32),
+                                       np.array([0, 3, 6], np.int32), 101, 2541, 2 ** 31 - 1)
+    assert len(tiles) == 3 + 1 and ng == 0 and npart == 0
+    assert all(int(t[2]) == 0 and int(t[6]) == 1 for t in tiles)
+
+
 def test_batch_plan_rejects_bad_input(semb):
     import numpy as np
     with pytest.raises(semb.SembError):

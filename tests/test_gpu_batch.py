@@ -98,6 +98,30 @@ def test_batch_equals_per_kind_scans(split, w_cmp, w_crs):
     _say("batch == per-kind scans", b.ntiles, "tiles", b.ng, "groups")
 
 
+def test_tiles_outside_the_given_plan_sizes_are_skipped():
+    """Called with ngroups = nparts = 0 for a plan whose CRS tiles are split
+    into groups, the kernel skips every split tile (their rows stay unwritten)
+    and still computes the unsplit CMP tiles exactly.  The workspace is sized
+    for the real plan, so every address the call could form stays inside it."""
+    import torch
+    import paper_1907_11678_amd as semb
+    bw = synth.batched_line(ids=range(2000, 2012))
+    b = Batch(bw, 256)
+    assert b.ng > 0 and b.np > 0
+    semb.scan_batch(b.dg, b.dj, b.kind, b.qc, bw.w_cmp, b.A, b.B, b.qr, bw.w_crs, b.tiles, 0, 0,
+                    b.best, b.sb, b.st, b.ws)
+    torch.cuda.synchronize()
+    best, sb, st = b.outputs()
+    crs_rows, cmp_rows = _kind_rows(bw, 1), _kind_rows(bw, 0)
+    assert (best[crs_rows] == -7).all() and np.isnan(sb[crs_rows]).all()
+    sub = bw.subset(0)
+    ref = gu.run_scan("cmp", bw.gathers, sub, bw.grid_cmp, bw.w_cmp, dg=b.dg,
+                      dj=gu.device_inputs(bw.gathers, sub)[1])
+    assert np.array_equal(best[cmp_rows], ref[0][cmp_rows])
+    assert np.array_equal(sb[cmp_rows], ref[1][cmp_rows])
+    _say("skipped", len(crs_rows), "CRS rows of split tiles; CMP rows equal the per-kind scan")
+
+
 def test_batch_matches_oracle_on_sampled_rows():
     import torch
     bw = synth.batched_line(ids=range(600, 624))
