@@ -580,6 +580,8 @@ semb_status semb_theta_from_best(const int32_t *best, int64_t n_out, const float
     if (n_out == 0) return SEMB_OK;
     if (!best || !q || nq < 1 || !theta) return fail(SEMB_EINVAL, "best, q and theta are required, nq >= 1");
     if ((A && nA < 1) || (B && nB < 1)) return fail(SEMB_EINVAL, "nA and nB must be >= 1");
+    if ((long long)(A ? nA : 1) * (B ? nB : 1) * nq > 0x7fffffffLL)
+        return fail(SEMB_EINVAL, "too many parameters");
     return hip_status(semb::launch_theta_from_best(best, n_out, A, A ? nA : 1, B, B ? nB : 1, q, nq, theta, stream),
                       "semb_theta_from_best launch");
 }

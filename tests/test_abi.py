@@ -159,6 +159,7 @@ def test_refinement_peaks_best_of_and_corrected_gathers_validate(semb):
     assert L.semb_theta_from_best(P, 10, None, 0, None, 0, None, 4, P, None) == 1             # no q
     assert L.semb_theta_from_best(P, 10, None, 0, None, 0, P, 0, P, None) == 1                # nq
     assert L.semb_theta_from_best(P, 10, P, 0, P, 2, P, 4, P, None) == 1                      # nA with A
+    assert L.semb_theta_from_best(P, 10, P, 70000, P, 70000, P, 4, P, None) == 1              # grid size
 
     assert L.semb_corrected_gathers(C.byref(g), C.byref(j), 5, P, P, P, None) == 1            # kind
     assert L.semb_corrected_gathers(C.byref(g), C.byref(j), 0, None, P, P, None) == 1         # no theta
