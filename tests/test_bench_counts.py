@@ -47,3 +47,16 @@ def test_crs_valid_fraction_is_exact():
 
 def test_eq2_flops():
     assert bench.eq2_flops(10, 7, 9) == 120 + 7 * 9 * 7
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The bench measures one GPU; asking for more exits with a message before
+    touching any device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in (r.stdout + r.stderr)
