@@ -86,9 +86,10 @@ def test_ragged_cmp(w):
                                      s_tol=gu.s_tol(w)))
 
 
-@pytest.mark.parametrize("w", [1, 5, 9])
+@pytest.mark.parametrize("w", [1, 5, 9, 11, 15])
 def test_ragged_crs_with_negative_radicands(w):
-    """Uneven line, +-2 aperture truncated at the ends, B < 0 large enough for T < 0."""
+    """Uneven line, +-2 aperture truncated at the ends, B < 0 large enough for T < 0.
+    The default CRS tile holds 4 parameters per wave up to w 9 and 2 above."""
     rng = np.random.default_rng(200 + w)
     gs = helpers.random_line(rng, 9, fold_range=(1, 5), ns_range=(30, 260), hmax=400.0, smooth=True)
     jobs = synth.line_crs_jobs(gs, list(range(9)), 2)
