@@ -191,6 +191,21 @@ def _typed(t, dtype, name):
     return _ptr(t)
 
 
+def _need(t, n: int, name: str):
+    """The library writes or reads n elements of t: refuse a smaller tensor
+    before anything is enqueued (the C ABI sees only the pointer)."""
+    if t is not None and int(t.numel()) < int(n):
+        raise ValueError(f"{name} has {int(t.numel())} elements; the call needs {int(n)}")
+
+
+def _scan_outputs(jobs: "DeviceJobs", npar: int, best, s_best, stack_out, panel=None, panel_f16=None):
+    n = jobs.n_out if jobs.njobs > 0 else 0
+    for t, name in ((best, "best"), (s_best, "s_best"), (stack_out, "stack_out")):
+        _need(t, n, name)
+    _need(panel, n * npar, "panel")
+    _need(panel_f16, n * npar, "panel_f16")
+
+
 def _stream(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -309,6 +324,7 @@ def cmp_scan(g: DeviceGathers, jobs: DeviceJobs, q, w: int, best, s_best, stack_
     """Enqueue the CMP scan; results land in best / s_best / stack_out (/ panel,
     panel_f16)."""
     import torch
+    _scan_outputs(jobs, int(q.numel()), best, s_best, stack_out, panel, panel_f16)
     gs, js, out = g.cstruct(), jobs.cstruct(), _outputs(best, s_best, stack_out, panel, panel_f16)
     _check(lib().cmp_scan(C.byref(gs), C.byref(js), _typed(q, torch.float32, "q"), int(q.numel()),
                           int(w), C.byref(out), _ptr(ws), int(ws.numel() * ws.element_size()),
@@ -319,6 +335,7 @@ def crs_scan(g: DeviceGathers, jobs: DeviceJobs, A, B, q, w: int, best, s_best, 
              panel=None, stream=None, panel_f16=None):
     """Enqueue the 2D CRS scan (flat parameter index (iA*nB + iB)*nq + iq)."""
     import torch
+    _scan_outputs(jobs, int(A.numel()) * int(B.numel()) * int(q.numel()), best, s_best, stack_out, panel, panel_f16)
     gs, js, out = g.cstruct(), jobs.cstruct(), _outputs(best, s_best, stack_out, panel, panel_f16)
     _check(lib().crs_scan(C.byref(gs), C.byref(js), _typed(A, torch.float32, "A"), int(A.numel()),
                           _typed(B, torch.float32, "B"), int(B.numel()),
@@ -329,6 +346,10 @@ def crs_scan(g: DeviceGathers, jobs: DeviceJobs, A, B, q, w: int, best, s_best, 
 def stack(g: DeviceGathers, jobs: DeviceJobs, kind: int, theta, w: int, s_out, stack_out, stream=None):
     """Semblance and stack at theta[row] = (A, B, q) for every output row."""
     import torch
+    n = jobs.n_out if jobs.njobs > 0 else 0
+    _need(theta, 3 * n, "theta")
+    _need(s_out, n, "s_out")
+    _need(stack_out, n, "stack_out")
     gs, js = g.cstruct(), jobs.cstruct()
     _check(lib().stack(C.byref(gs), C.byref(js), int(kind), _typed(theta, torch.float32, "theta"),
                        int(w), _typed(s_out, torch.float32, "s_out"),
@@ -339,6 +360,11 @@ def semblance_grad(g: DeviceGathers, jobs: DeviceJobs, kind: int, theta, g_s, w:
                    g_samples=None, stream=None):
     """dL/dtheta (overwritten) and dL/dsamples (accumulated) for L = sum g_s * S."""
     import torch
+    n = jobs.n_out if jobs.njobs > 0 else 0
+    _need(theta, 3 * n, "theta")
+    _need(g_s, n, "g_s")
+    _need(g_theta, 3 * n, "g_theta")
+    _need(g_samples, g.nsamples, "g_samples")
     gs, js = g.cstruct(), jobs.cstruct()
     _check(lib().semblance_grad(C.byref(gs), C.byref(js), int(kind),
                                 _typed(theta, torch.float32, "theta"),
@@ -398,11 +424,12 @@ def tune_scan(kind: int, g: DeviceGathers, jobs: DeviceJobs, q, w: int, best, s_
     whose outputs equal the default shape's, and return (shape, [ms per shape]
     with -1 for excluded shapes).  Synchronizes the stream."""
     import torch
+    nA = int(A.numel()) if A is not None else 1
+    nB = int(B.numel()) if B is not None else 1
+    _scan_outputs(jobs, (nA * nB if kind == KIND_CRS else 1) * int(q.numel()), best, s_best, stack_out)
     gs, js, out = g.cstruct(), jobs.cstruct(), _outputs(best, s_best, stack_out, None)
     shape = C.c_int32(-1)
     ms = (C.c_float * SCAN_SHAPES)()
-    nA = int(A.numel()) if A is not None else 1
-    nB = int(B.numel()) if B is not None else 1
     _check(lib().semb_tune_scan(C.byref(gs), C.byref(js), int(kind),
                                 _typed(A, torch.float32, "A") if A is not None else None, nA,
                                 _typed(B, torch.float32, "B") if B is not None else None, nB,
@@ -467,6 +494,10 @@ def scan_batch(g: DeviceGathers, jobs: DeviceJobs, kind, q_cmp, w_cmp: int, A, B
                ngroups: int, nparts: int, best, s_best, stack_out, ws, stream=None):
     """Enqueue the batched scan; tiles: device int32 [ntiles, 8] from batch_plan."""
     import torch
+    _scan_outputs(jobs, 0, best, s_best, stack_out)
+    _need(kind, jobs.njobs, "kind")
+    if tiles.dim() != 2 or int(tiles.shape[1]) != 8:
+        raise ValueError("tiles must be [ntiles, 8] as batch_plan returns them")
     gs, js = g.cstruct(), jobs.cstruct()
     b = CBatch(_typed(kind, torch.int32, "kind"), _typed(q_cmp, torch.float32, "q_cmp"), int(q_cmp.numel()),
                int(w_cmp), _typed(A, torch.float32, "A"), int(A.numel()), _typed(B, torch.float32, "B"),
@@ -483,6 +514,7 @@ def scan_batch(g: DeviceGathers, jobs: DeviceJobs, kind, q_cmp, w_cmp: int, A, B
 def theta_from_best(best, q, theta, A=None, B=None, stream=None):
     """theta[row] = grid parameter (A, B, q) of the flat index best[row]."""
     import torch
+    _need(theta, 3 * int(best.numel()), "theta")
     _check(lib().semb_theta_from_best(_typed(best, torch.int32, "best"), int(best.numel()),
                                       _typed(A, torch.float32, "A"), int(A.numel()) if A is not None else 1,
                                       _typed(B, torch.float32, "B"), int(B.numel()) if B is not None else 1,
@@ -495,6 +527,10 @@ def refine(g: DeviceGathers, jobs: DeviceJobs, kind: int, theta, w: int, s_out, 
            stream=None, grow: float = 1.25):
     """Gradient-ascent refinement of theta [n_out, 3] in place (see semb_refine)."""
     import torch
+    n = jobs.n_out if jobs.njobs > 0 else 0
+    _need(theta, 3 * n, "theta")
+    _need(s_out, n, "s_out")
+    _need(stack_out, n, "stack_out")
     gs, js = g.cstruct(), jobs.cstruct()
     o = CRefineOpts(int(steps), float(eta0), float(grow), (C.c_float * 3)(*scale), (C.c_float * 3)(*lo),
                     (C.c_float * 3)(*hi))
@@ -525,8 +561,11 @@ def corrected_offsets(trace_ptr, ns, central, apert_ptr=None, apert_gather=None)
 
 
 def corrected_gathers(g: DeviceGathers, jobs: DeviceJobs, kind: int, theta, corr_off, out, stream=None):
-    """Every job's aperture traces read along theta[row] (see semb_corrected_gathers)."""
+    """Every job's aperture traces read along theta[row] (see semb_corrected_gathers);
+    out must hold the total that corrected_offsets returns."""
     import torch
+    _need(theta, 3 * (jobs.n_out if jobs.njobs > 0 else 0), "theta")
+    _need(corr_off, jobs.njobs, "corr_off")
     gs, js = g.cstruct(), jobs.cstruct()
     _check(lib().semb_corrected_gathers(C.byref(gs), C.byref(js), int(kind), _typed(theta, torch.float32, "theta"),
                                         _typed(corr_off, torch.int64, "corr_off"), _typed(out, torch.float32, "out"),
@@ -538,6 +577,9 @@ def panel_peaks(panel, nA: int, nB: int, nq: int, K: int, best_k, s_k, stream=No
     best_k, s_k: [K, n_rows]."""
     import torch
     n = int(panel.shape[0])
+    _need(panel, n * int(nA) * int(nB) * int(nq), "panel")
+    _need(best_k, int(K) * n, "best_k")
+    _need(s_k, int(K) * n, "s_k")
     _check(lib().semb_panel_peaks(_typed(panel, torch.float32, "panel"), n, int(nA), int(nB), int(nq), int(K),
                                   _typed(best_k, torch.int32, "best_k"), _typed(s_k, torch.float32, "s_k"),
                                   _stream(stream)))
@@ -548,6 +590,11 @@ def best_of(s_k, stack_k, theta_k, s_out, stack_out, theta_out, stream=None):
     theta_k [K, n, 3] -> s_out, stack_out [n], theta_out [n, 3]."""
     import torch
     K, n = int(s_k.shape[0]), int(s_k.shape[1])
+    _need(stack_k, K * n, "stack_k")
+    _need(theta_k, 3 * K * n, "theta_k")
+    _need(s_out, n, "s_out")
+    _need(stack_out, n, "stack_out")
+    _need(theta_out, 3 * n, "theta_out")
     _check(lib().semb_best_of(K, n, _typed(s_k, torch.float32, "s_k"), _typed(stack_k, torch.float32, "stack_k"),
                               _typed(theta_k, torch.float32, "theta_k"), _typed(s_out, torch.float32, "s_out"),
                               _typed(stack_out, torch.float32, "stack_out"),
