@@ -242,6 +242,12 @@ class DeviceGathers:
 
     def cstruct(self) -> CGathers:
         import torch
+        ng, nt = self.ngathers, self.ntraces
+        for t, n, name in ((self.sample_off, ng, "sample_off"), (self.trace_ptr, ng + 1, "trace_ptr"),
+                           (self.central_x, ng, "central_x"), (self.midpoint, nt, "midpoint")):
+            if t is not None and int(t.numel()) != n:
+                raise ValueError(f"gathers.{name} has {int(t.numel())} elements; {n} expected "
+                                 f"({ng} gathers, {nt} traces)")
         return CGathers(_typed(self.samples, torch.float32, "samples"),
                         _typed(self.sample_off, torch.int64, "sample_off"),
                         _typed(self.trace_ptr, torch.int32, "trace_ptr"),
@@ -267,6 +273,10 @@ class DeviceJobs:
 
     def cstruct(self) -> CJobs:
         import torch
+        nj = self.njobs
+        for t, n, name in ((self.out_off, nj, "out_off"), (self.apert_ptr, nj + 1, "apert_ptr")):
+            if t is not None and int(t.numel()) != n:
+                raise ValueError(f"jobs.{name} has {int(t.numel())} elements; {n} expected ({nj} jobs)")
         return CJobs(_typed(self.central, torch.int32, "central"),
                      _typed(self.apert_ptr, torch.int32, "apert_ptr"),
                      _typed(self.apert_gather, torch.int32, "apert_gather"),

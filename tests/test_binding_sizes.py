@@ -66,3 +66,23 @@ def test_no_jobs_needs_no_outputs():
     with pytest.raises(ValueError, match="GPU"):
         semb.cmp_scan(g, j, torch.zeros(7), 11, torch.zeros(0, dtype=torch.int32), torch.zeros(0),
                       torch.zeros(0), torch.zeros(16))
+
+
+def test_gathers_and_jobs_arrays_must_agree_in_length():
+    g, j = _inputs()
+    g.trace_ptr = torch.zeros(2, dtype=torch.int32)  # 2 gathers need 3 entries
+    with pytest.raises(ValueError, match="trace_ptr"):
+        g.cstruct()
+    g, j = _inputs()
+    g.midpoint = torch.zeros(9)  # 10 traces
+    with pytest.raises(ValueError, match="midpoint"):
+        g.cstruct()
+    g, j = _inputs()
+    j.out_off = torch.zeros(3, dtype=torch.int64)  # 2 jobs
+    with pytest.raises(ValueError, match="out_off"):
+        j.cstruct()
+    j = semb.DeviceJobs(central=torch.zeros(2, dtype=torch.int32), apert_ptr=torch.zeros(2, dtype=torch.int32),
+                        apert_gather=torch.zeros(2, dtype=torch.int32), out_off=torch.zeros(2, dtype=torch.int64),
+                        max_apert=1, n_out=10)
+    with pytest.raises(ValueError, match="apert_ptr"):
+        j.cstruct()
