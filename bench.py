@@ -252,7 +252,22 @@ def main():
             "algorithmic_bytes_per_launch": 4 * (gs.samples.size + h.size + 3 * n),
         },
     }
-    del dg, ws, host
+    # PCIe context (never `value`): the samples' host-to-device copy from pinned
+    # memory, timed on its own after the step, and the rate a caller who
+    # uploads the data for every step would see
+    dst = torch.empty_like(dg.samples)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dst.copy_(host, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d = time.perf_counter() - t0
+    out["pcie"] = {"h2d_bytes": host.numel() * 4, "h2d_ms": h2d * 1e3,
+                   "h2d_gb_per_s": host.numel() * 4 / h2d / 1e9,
+                   "evals_per_s_with_upload": evals / (ms_per_step * 1e-3 + h2d)}
+    log(f"pcie: {host.numel() * 4 / 1e9:.2f} GB host-to-device in {h2d * 1e3:.1f} ms "
+        f"({host.numel() * 4 / h2d / 1e9:.1f} GB/s); with the upload in every step "
+        f"{out['pcie']['evals_per_s_with_upload']:.3e} evals/s")
+    del dst, dg, ws, host
     torch.cuda.empty_cache()
 
     legs = set() if args.cmp_only else {x.strip() for x in args.legs.split(",") if x.strip()}
