@@ -274,3 +274,63 @@ def test_fp16_panel_is_the_rounded_fp32_panel(kind):
                       best, sb, st, ws, panel=p32, panel_f16=p16)
     torch.cuda.synchronize()
     assert torch.equal(p16, p32.half())
+
+
+@pytest.mark.parametrize("kind", ["cmp", "crs"])
+def test_scan_graph_replay(kind):
+    """Capture a scan (window-energy pass and scan kernel, FP32 and FP16
+    panels) in a HIP graph; replay it three times with eager work and
+    synchronisations in between, and check every replay bit for bit against
+    the eager call."""
+    import torch
+    import paper_1907_11678_amd as semb
+    if kind == "cmp":
+        wl = synth.cmp_plain(ids=list(range(8)))
+    else:
+        wl = synth.crs_line(centrals=list(range(20, 26)), grid=synth.crs_coarse_grid())
+    gs, jobs = wl.gathers, wl.jobs
+    dg, dj = gu.device_inputs(gs, jobs)
+    n = jobs.n_out
+    npar = wl.grid.n if kind == "crs" else wl.grid.q.size
+    best = torch.empty(n, dtype=torch.int32, device="cuda")
+    sb, st = torch.empty(n, device="cuda"), torch.empty(n, device="cuda")
+    pan = torch.empty(n * npar, device="cuda")
+    p16 = torch.empty(n * npar, dtype=torch.float16, device="cuda")
+    ws = semb.alloc_workspace(dg.nsamples)
+    q = torch.from_numpy(wl.grid.q).cuda()
+    A = torch.from_numpy(wl.grid.A).cuda() if kind == "crs" else None
+    B = torch.from_numpy(wl.grid.B).cuda() if kind == "crs" else None
+
+    def run(stream=None):
+        if kind == "cmp":
+            semb.cmp_scan(dg, dj, q, wl.w, best, sb, st, ws, panel=pan, panel_f16=p16, stream=stream)
+        else:
+            semb.crs_scan(dg, dj, A, B, q, wl.w, best, sb, st, ws, panel=pan, panel_f16=p16, stream=stream)
+
+    def snap():
+        return [t.cpu().numpy().copy() for t in (best, sb, st, pan, p16)]
+
+    run()
+    torch.cuda.synchronize()
+    eager = snap()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run(stream=s)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        run(stream=s)
+    for k in range(3):
+        for t in (best, sb, st, pan, p16):
+            t.zero_()
+        ws.fill_(7)  # the replay must recompute the energy planes
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a_, e_ in zip(snap(), eager):
+            assert np.array_equal(a_, e_, equal_nan=True), f"{kind} replay {k} differs"
+        del junk
+    _say(kind, "graph replays equal the eager scan,", n, "rows x", npar, "parameters")
