@@ -334,3 +334,45 @@ def test_scan_graph_replay(kind):
             assert np.array_equal(a_, e_, equal_nan=True), f"{kind} replay {k} differs"
         del junk
     _say(kind, "graph replays equal the eager scan,", n, "rows x", npar, "parameters")
+
+
+def test_concurrent_scans_on_two_streams():
+    """Two scans with their own workspaces and outputs, enqueued on two streams
+    so that they can overlap, give exactly what each gives alone."""
+    import torch
+    import paper_1907_11678_amd as semb
+    wl1 = synth.cmp_plain(ids=list(range(16)))
+    wl2 = synth.crs_line(centrals=list(range(30, 34)), grid=synth.crs_coarse_grid())
+    d1 = gu.device_inputs(wl1.gathers, wl1.jobs)
+    d2 = gu.device_inputs(wl2.gathers, wl2.jobs)
+    q1 = torch.from_numpy(wl1.grid.q).cuda()
+    A2, B2, q2 = (torch.from_numpy(x).cuda() for x in (wl2.grid.A, wl2.grid.B, wl2.grid.q))
+
+    def bufs(n, dg):
+        return (torch.empty(n, dtype=torch.int32, device="cuda"), torch.empty(n, device="cuda"),
+                torch.empty(n, device="cuda"), semb.alloc_workspace(dg.nsamples))
+
+    def run1(o, stream=None):
+        semb.cmp_scan(d1[0], d1[1], q1, wl1.w, o[0], o[1], o[2], o[3], stream=stream)
+
+    def run2(o, stream=None):
+        semb.crs_scan(d2[0], d2[1], A2, B2, q2, wl2.w, o[0], o[1], o[2], o[3], stream=stream)
+
+    a1, a2 = bufs(wl1.jobs.n_out, d1[0]), bufs(wl2.jobs.n_out, d2[0])
+    run1(a1)
+    torch.cuda.synchronize()
+    run2(a2)
+    torch.cuda.synchronize()
+    ref1 = [t.cpu().numpy().copy() for t in a1[:3]]
+    ref2 = [t.cpu().numpy().copy() for t in a2[:3]]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    b1, b2 = bufs(wl1.jobs.n_out, d1[0]), bufs(wl2.jobs.n_out, d2[0])
+    for _ in range(3):
+        s1.wait_stream(torch.cuda.current_stream())
+        s2.wait_stream(torch.cuda.current_stream())
+        run1(b1, stream=s1)
+        run2(b2, stream=s2)
+        torch.cuda.synchronize()
+        for got, ref in ((b1, ref1), (b2, ref2)):
+            for a_, e_ in zip([t.cpu().numpy() for t in got[:3]], ref):
+                assert np.array_equal(a_, e_)
