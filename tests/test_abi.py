@@ -314,3 +314,35 @@ def test_tuner_rejects_bad_arguments(semb):
 def test_shape_count_matches_the_header(semb):
     text = open(HEADER).read()
     assert f"#define SEMB_SCAN_SHAPES {semb.SCAN_SHAPES}" in text
+
+
+def test_shape_table_under_concurrent_threads(semb):
+    """The tuner's process-wide table is guarded by a mutex: threads that set,
+    read and clear their own keys concurrently (ctypes releases the GIL during
+    the calls) each see their own entries."""
+    import threading
+    L = semb.lib()
+    L.semb_clear_tuning()
+    errors = []
+
+    def worker(k):
+        g = _gathers(semb, ntraces=600, ngathers=20, ns_max=64 << (k % 4))
+        j = _jobs(semb, max_apert=9)
+        w = 2 * k + 1
+        try:
+            for it in range(2000):
+                shape = (k + it) % semb.SCAN_SHAPES
+                assert L.semb_set_scan_shape(k % 2, w, C.byref(g), C.byref(j), shape) == 0
+                got = L.semb_scan_shape(k % 2, w, C.byref(g), C.byref(j))
+                assert got == shape, (k, it, got, shape)
+            assert L.semb_set_scan_shape(k % 2, w, C.byref(g), C.byref(j), -1) == 0
+        except AssertionError as e:  # pragma: no cover - reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(8)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors[:3]
+    L.semb_clear_tuning()
