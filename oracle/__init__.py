@@ -44,18 +44,20 @@ class Library:
         P = C.c_void_p
         i32, f64 = C.c_int32, C.c_double
         common = [C.c_int, P, P, P, P, P, P, P, f64, i32, P, P, P, P]
-        L.oracle_scan.argtypes = common + [P, i32, P, i32, P, i32, i32, P, P, P, P, P, P, C.c_int]
+        L.oracle_scan.argtypes = common + [P, i32, P, i32, P, i32, i32, P, P, P, P, P, P, P, P, C.c_int]
         L.oracle_point.argtypes = common + [P, i32, P, P, P, P, C.c_int]
-        L.oracle_grad.argtypes = common + [P, P, i32, P, P, C.c_int]
+        L.oracle_grad.argtypes = common + [P, P, i32, P, P, P, P, P, P, C.c_int]
         L.oracle_corrected.argtypes = common + [P, P, P, C.c_int]
         L.oracle_corrected.restype = C.c_int
         L.oracle_scan_rows.argtypes = [C.c_int, P, P, P, P, P, P, P, f64, i32, P, P, P, P, P,
-                                       P, i32, P, i32, P, i32, i32, P, P, P, P, P, C.c_int]
+                                       P, i32, P, i32, P, i32, i32, P, P, P, P, P, P, C.c_int]
         for f in (L.oracle_scan, L.oracle_point, L.oracle_grad, L.oracle_scan_rows):
             f.restype = C.c_int
         L.oracle_max_threads.restype = C.c_int
         L.oracle_set_fragility.argtypes = [C.c_double, C.c_double]
         L.oracle_set_fragility.restype = None
+        L.oracle_set_kink.argtypes = [C.c_double]
+        L.oracle_set_kink.restype = None
         self.L = L
         self.path = path
 
@@ -89,6 +91,15 @@ FRAGILE_DEFAULT = (1e-3, 1e-6)
 def set_fragility(tau_samples: float, t_rel: float, library: Library | None = None):
     """Set the perturbations that flag a cell as fragile (see oracle.c)."""
     (library or lib()).L.oracle_set_fragility(float(tau_samples), float(t_rel))
+
+
+KINK_DEFAULT = 1e-4
+
+
+def set_kink(tau_samples: float, library: Library | None = None):
+    """Set the distance (samples) of a contributing intersection from an
+    integer that flags its cell as a kink of the gradient (see oracle.c)."""
+    (library or lib()).L.oracle_set_kink(float(tau_samples))
 
 
 def max_threads() -> int:
@@ -133,6 +144,8 @@ class ScanResult:
     gap: np.ndarray      # float64 [n_out] best S minus runner-up S
     fragile: np.ndarray  # bool [n_out]
     panel: np.ndarray | None  # float64 [n_out, n_params]
+    cond: np.ndarray | None = None  # float64 [n_out] condition number of S at the pick
+    panel_cond: np.ndarray | None = None  # float64 [n_out, n_params] of every cell (with panel)
 
 
 def _n_out(jobs) -> int:
@@ -151,13 +164,15 @@ def scan(kind, gs, jobs, grid, w: int, panel: bool = False, nthreads: int | None
     st = np.zeros(n, np.float64)
     gap = np.zeros(n, np.float64)
     fr = np.zeros(n, np.uint8)
+    cond = np.zeros(n, np.float64)
     pan = np.zeros((n, npar), np.float64) if panel else None
+    pcond = np.zeros((n, npar), np.float64) if panel else None
     rc = (library or lib()).L.oracle_scan(*a.head(), _p(A), A.size, _p(B), B.size, _p(q), q.size, int(w),
-                           _p(best), _p(sb), _p(st), _p(pan), _p(gap), _p(fr),
+                           _p(best), _p(sb), _p(st), _p(pan), _p(gap), _p(fr), _p(cond), _p(pcond),
                            int(nthreads or max_threads()))
     if rc != 0:
         raise ValueError("oracle_scan: invalid arguments")
-    return ScanResult(best, sb, st, gap, fr.astype(bool), pan)
+    return ScanResult(best, sb, st, gap, fr.astype(bool), pan, cond, pcond)
 
 
 def scan_rows(kind, gs, jobs, grid, w: int, row_job, row_s, nthreads: int | None = None,
@@ -174,15 +189,16 @@ def scan_rows(kind, gs, jobs, grid, w: int, row_job, row_s, nthreads: int | None
     st = np.zeros(n, np.float64)
     gap = np.zeros(n, np.float64)
     fr = np.zeros(n, np.uint8)
+    cond = np.zeros(n, np.float64)
     k = a.keep
     j = a.jobs
     rc = (library or lib()).L.oracle_scan_rows(
         a.kind, _p(k[0]), _p(k[1]), _p(k[2]), _p(k[3]), _p(k[4]), _p(k[5]), _p(k[6]), a.dt, n,
         _p(rj), _p(rs), _p(j[0]), _p(j[1]), _p(j[2]), _p(A), A.size, _p(B), B.size, _p(q), q.size,
-        int(w), _p(best), _p(sb), _p(st), _p(gap), _p(fr), int(nthreads or max_threads()))
+        int(w), _p(best), _p(sb), _p(st), _p(gap), _p(fr), _p(cond), int(nthreads or max_threads()))
     if rc != 0:
         raise ValueError("oracle_scan_rows: invalid arguments")
-    return ScanResult(best, sb, st, gap, fr.astype(bool), None)
+    return ScanResult(best, sb, st, gap, fr.astype(bool), None, cond)
 
 
 def point(kind, gs, jobs, theta: np.ndarray, w: int, nthreads: int | None = None,
@@ -203,20 +219,40 @@ def point(kind, gs, jobs, theta: np.ndarray, w: int, nthreads: int | None = None
     return s, st, m, fr.astype(bool)
 
 
+@dataclass
+class GradDetail:
+    """Sizes and flags that go with a gradient (see oracle_grad)."""
+    g_theta_mag: np.ndarray      # [n_out, 3] the gradient's terms summed by magnitude
+    g_samples_mag: np.ndarray    # [n_samples] same for the sample gradient
+    rough: np.ndarray            # bool [n_out] kink or fragile row
+    samples_rough: np.ndarray    # bool [n_samples] read by a rough row's windows
+
+
 def grad(kind, gs, jobs, theta: np.ndarray, g_s: np.ndarray, w: int, samples_grad: bool = True,
-         nthreads: int | None = None, library: Library | None = None):
-    """dL/dtheta [n_out, 3] and dL/dsamples (or None) for L = sum g_s * S(theta)."""
+         nthreads: int | None = None, library: Library | None = None, detail: bool = False):
+    """dL/dtheta [n_out, 3] and dL/dsamples (or None) for L = sum g_s * S(theta);
+    with detail=True also a GradDetail."""
     a = _Args(kind, gs, jobs)
     n = _n_out(jobs)
     th = _c(theta, np.float64).reshape(n, 3)
     gsv = _c(g_s, np.float64).reshape(n)
     gt = np.zeros((n, 3), np.float64)
-    gsm = np.zeros(gs.samples.shape[0], np.float64) if samples_grad else None
-    rc = (library or lib()).L.oracle_grad(*a.head(), _p(th), _p(gsv), int(w), _p(gt), _p(gsm),
-                           int(nthreads or max_threads()))
+    nsm = gs.samples.shape[0]
+    gsm = np.zeros(nsm, np.float64) if samples_grad else None
+    d = GradDetail(np.zeros((n, 3)), np.zeros(nsm), np.zeros(n, np.uint8), np.zeros(nsm, np.uint8)) \
+        if detail else None
+    rc = (library or lib()).L.oracle_grad(
+        *a.head(), _p(th), _p(gsv), int(w), _p(gt), _p(gsm),
+        _p(d.g_theta_mag) if d else None, _p(d.g_samples_mag) if d else None,
+        _p(d.rough) if d else None, _p(d.samples_rough) if d else None,
+        int(nthreads or max_threads()))
     if rc != 0:
         raise ValueError("oracle_grad: invalid arguments")
-    return gt, gsm
+    if d is None:
+        return gt, gsm
+    d.rough = d.rough.astype(bool)
+    d.samples_rough = d.samples_rough.astype(bool)
+    return gt, gsm, d
 
 
 def corrected_offsets(gs, jobs) -> tuple[np.ndarray, int]:

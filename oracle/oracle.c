@@ -76,6 +76,17 @@ void oracle_set_fragility(double tau_samples, double t_rel)
     FRAGILE_T_REL = t_rel;
 }
 
+/* A contributing intersection within KINK_TAU samples of an integer marks its
+ * cell as a kink of the gradient: the window's interpolation segments, and so
+ * the slopes dv/dtau, change there.  The default suits a gradient compared
+ * with central differences whose step moves tau by less than 1e-4 samples. */
+static double KINK_TAU = 1e-4;
+
+void oracle_set_kink(double tau_samples)
+{
+    KINK_TAU = tau_samples;
+}
+
 typedef struct {
     const float *samples;
     const int64_t *sample_off;
@@ -120,6 +131,7 @@ typedef struct {
     double S, stack, D, N, L;
     int M;
     int fragile;
+    int kink;
 } cell_t;
 
 /* The accumulators of one (job, t0, theta) cell, traces in ascending order:
@@ -132,6 +144,7 @@ static cell_t eval_cell(const gset *g, int kind, int central, const int32_t *ag,
     const double t0 = s * g->dt;
     const double xc = (kind == ORACLE_CRS) ? (double)g->central_x[central] : 0.0;
     for (int j = 0; j < w; j++) U[j] = 0.0;
+    c.kink = 0;
 
     for (int p = 0; p < na; p++) {
         const int gg = ag[p];
@@ -162,6 +175,10 @@ static cell_t eval_cell(const gset *g, int kind, int central, const int32_t *ag,
             const double kf = floor(tau);
             const double x = tau - kf;
             const int64_t a = (int64_t)kf - hw;
+            /* a kink: moving the intersection by KINK_TAU samples would read the
+             * window from the neighbouring interpolation segments, whose slopes
+             * differ (the derivative in theta jumps there) */
+            if (x < KINK_TAU || x > 1.0 - KINK_TAU) c.kink = 1;
             for (int j = 0; j < w; j++) {
                 const double f0 = f[a + j], f1 = f[a + j + 1];
                 const double v = f0 + x * (f1 - f0);
@@ -176,6 +193,58 @@ static cell_t eval_cell(const gset *g, int kind, int central, const int32_t *ag,
     c.S = (c.M > 0 && c.D > 0.0) ? c.N / ((double)c.M * c.D) : 0.0;
     c.stack = (c.M > 0) ? c.L / ((double)c.M * (double)w) : 0.0;
     return c;
+}
+
+/* Condition number of S at one cell, for the tolerance of a comparison with
+ * an FP32 evaluation of the same definition.  S = N / (M D) is formed from two
+ * separate sums, N = sum_j U_j^2 and D, whose roundings are independent, so
+ * each is perturbed on its own: every term of U_j by the magnitude of the two
+ * samples it is interpolated from, and every trace's energy D_i = sum_j v_ij^2
+ * by 2 sqrt(D_i) (|A_i| + |A'_i|), A_i and A'_i the norms of the window's
+ * samples f[a..a+w-1] and f[a+1..a+w]:
+ *   kappa = sum_i [ sum_j |dS/dU_j| (|f[a+j]| + |f[a+j+1]|)
+ *                   + |dS/dD| 2 sqrt(D_i) (|A_i| + |A'_i|) ],
+ * dS/dU_j = 2 U_j / (M D), dS/dD = -S / D.  Rounding the samples, the
+ * interpolation and the energies to FP32 (relative error ~2^-24) moves S by
+ * about 2^-24 kappa.  U holds the cell's window sums (eval_cell); 0 when S is
+ * identically 0. */
+static double cell_cond(const gset *g, int kind, int central, const int32_t *ag, int na, int s,
+                        theta_t th, int w, const double *U, cell_t cl)
+{
+    if (!(cl.M > 0 && cl.D > 0.0)) return 0.0;
+    const int hw = (w - 1) / 2;
+    const double t0 = s * g->dt;
+    const double xc = (kind == ORACLE_CRS) ? (double)g->central_x[central] : 0.0;
+    const double MD = (double)cl.M * cl.D;
+    double kappa = 0.0;
+    for (int p = 0; p < na; p++) {
+        const int gg = ag[p];
+        const int nsg = g->ns[gg];
+        for (int i = g->trace_ptr[gg]; i < g->trace_ptr[gg + 1]; i++) {
+            const float *f = g->samples + g->sample_off[gg] + (int64_t)(i - g->trace_ptr[gg]) * nsg;
+            const double h = g->half_offset[i];
+            const double dm = (kind == ORACLE_CRS) ? (double)g->midpoint[i] - xc : 0.0;
+            double mag;
+            const double T = traveltime_sq(kind, t0, th, dm, h, &mag);
+            if (T < 0.0) continue;
+            const double tau = sqrt(T) / g->dt;
+            if (!window_on_trace(tau, w, nsg)) continue;
+            const double kf = floor(tau);
+            const double x = tau - kf;
+            const int64_t a = (int64_t)kf - hw;
+            double Di = 0.0, nA = 0.0, nA1 = 0.0;
+            for (int j = 0; j < w; j++) {
+                const double f0 = f[a + j], f1 = f[a + j + 1];
+                const double v = f0 + x * (f1 - f0);
+                kappa += fabs(2.0 * U[j] / MD) * (fabs(f0) + fabs(f1));
+                Di += v * v;
+                nA += f0 * f0;
+                nA1 += f1 * f1;
+            }
+            kappa += cl.S / cl.D * 2.0 * sqrt(Di) * (sqrt(nA) + sqrt(nA1));
+        }
+    }
+    return kappa;
 }
 
 /* Row r of the output -> (job, sample). */
@@ -209,13 +278,29 @@ static int check_args(int kind, const gset *g, int w, int nA, int nB, int nq)
     return 0;
 }
 
+/* kappa (cell_cond) of the picked cell p of a row; flat p = (iA nB + iB) nq + iq. */
+static double pick_cond(const gset *g, int kind, int c, const int32_t *ag, int na, int s, const float *A,
+                        int32_t nA, const float *B, int32_t nB, const float *q, int32_t nq, int64_t p, int w,
+                        double *U)
+{
+    (void)nA;
+    theta_t th;
+    th.q = q[p % nq];
+    th.B = (kind == ORACLE_CRS) ? (double)B[(p / nq) % nB] : 0.0;
+    th.A = (kind == ORACLE_CRS) ? (double)A[p / ((int64_t)nq * nB)] : 0.0;
+    cell_t cl = eval_cell(g, kind, c, ag, na, s, th, w, U);
+    return cell_cond(g, kind, c, ag, na, s, th, w, U, cl);
+}
+
 /*
  * Exhaustive scan (section 3.2): for every job, output sample and flat
  * parameter index, the semblance; then per output row the pick, its
  * semblance and its stack.  Optional outputs: panel (row-major [row][param]),
- * gap (best S minus the best S of any other parameter) and fragile (1 if any
- * cell of the row is fragile).  Output row of (job j, sample s) is
- * out_off[j] + s.  Returns 0, or 1 for invalid arguments.
+ * gap (best S minus the best S of any other parameter), fragile (1 if any
+ * cell of the row is fragile), cond (cell_cond of the picked cell) and
+ * panel_cond (cell_cond of every cell, laid out like panel).  Output row of
+ * (job j, sample s) is out_off[j] + s.  Returns 0, or 1 for invalid
+ * arguments.
  */
 int oracle_scan(int kind, const float *samples, const int64_t *sample_off, const int32_t *trace_ptr,
                 const int32_t *ns, const float *half_offset, const float *midpoint,
@@ -223,7 +308,7 @@ int oracle_scan(int kind, const float *samples, const int64_t *sample_off, const
                 const int32_t *apert_ptr, const int32_t *apert_gather, const int64_t *out_off,
                 const float *A, int32_t nA, const float *B, int32_t nB, const float *q, int32_t nq,
                 int32_t w, int32_t *best, double *s_best, double *stack, double *panel, double *gap,
-                uint8_t *fragile, int nthreads)
+                uint8_t *fragile, double *cond, double *panel_cond, int nthreads)
 {
     gset g = {samples, sample_off, trace_ptr, ns, half_offset, midpoint, central_x, dt};
     if (check_args(kind, &g, w, nA, nB, nq)) return 1;
@@ -256,6 +341,8 @@ int oracle_scan(int kind, const float *samples, const int64_t *sample_off, const
                     cell_t cl = eval_cell(&g, kind, c, ag, na, s, th, w, Ub);
                     frag |= cl.fragile;
                     if (panel) panel[orow * npar + p] = cl.S;
+                    if (panel_cond)
+                        panel_cond[orow * npar + p] = cell_cond(&g, kind, c, ag, na, s, th, w, Ub, cl);
                     if (cl.S > s1) { /* strict: the first index wins ties */
                         s2 = s1;
                         s1 = cl.S;
@@ -270,6 +357,7 @@ int oracle_scan(int kind, const float *samples, const int64_t *sample_off, const
         stack[orow] = st1;
         if (gap) gap[orow] = (npar > 1) ? s1 - s2 : INFINITY;
         if (fragile) fragile[orow] = (uint8_t)frag;
+        if (cond) cond[orow] = pick_cond(&g, kind, c, ag, na, s, A, nA, B, nB, q, nq, p1, w, Ub);
         if (Ub != U) free(Ub);
     }
     free(rows);
@@ -287,7 +375,7 @@ int oracle_scan_rows(int kind, const float *samples, const int64_t *sample_off, 
                      const int32_t *row_s, const int32_t *job_central, const int32_t *apert_ptr,
                      const int32_t *apert_gather, const float *A, int32_t nA, const float *B, int32_t nB,
                      const float *q, int32_t nq, int32_t w, int32_t *best, double *s_best, double *stack,
-                     double *gap, uint8_t *fragile, int nthreads)
+                     double *gap, uint8_t *fragile, double *cond, int nthreads)
 {
     gset g = {samples, sample_off, trace_ptr, ns, half_offset, midpoint, central_x, dt};
     if (check_args(kind, &g, w, nA, nB, nq)) return 1;
@@ -326,6 +414,7 @@ int oracle_scan_rows(int kind, const float *samples, const int64_t *sample_off, 
         stack[r] = st1;
         if (gap) gap[r] = (npar > 1) ? s1 - s2 : INFINITY;
         if (fragile) fragile[r] = (uint8_t)frag;
+        if (cond) cond[r] = pick_cond(&g, kind, c, ag, na, s, A, nA, B, nB, q, nq, p1, w, Ub);
         if (Ub != U) free(Ub);
     }
     return 0;
@@ -439,13 +528,25 @@ int oracle_corrected(int kind, const float *samples, const int64_t *sample_off, 
  *   dv_ij/df[a+j] = 1 - x,  dv_ij/df[a+j+1] = x.
  * Rows with M = 0 or D = 0 (S identically 0) and traces with T = 0 (tau has
  * no derivative there) contribute nothing.
+ *
+ * Optional outputs for comparisons with an FP32 evaluation:
+ *  - g_theta_mag [row][3], g_samples_mag (ACCUMULATED): the same sums with
+ *    every term replaced by its magnitude and dS/dv_ij by its size before
+ *    the subtraction cancels, 2 (sum_i |v_ij| + S M |v_ij|) / (M D).  An
+ *    evaluation whose every term carries a relative error e differs by at
+ *    most about e times these;
+ *  - rough [row]: 1 if the row's cell is a kink (a contributing intersection
+ *    within KINK_TAU samples of an integer) or fragile (its contributing set
+ *    could change, as in oracle_scan);
+ *  - samples_rough: 1 on every sample a rough row's windows could read.
  */
 int oracle_grad(int kind, const float *samples, const int64_t *sample_off, const int32_t *trace_ptr,
                 const int32_t *ns, const float *half_offset, const float *midpoint,
                 const float *central_x, double dt, int32_t njobs, const int32_t *job_central,
                 const int32_t *apert_ptr, const int32_t *apert_gather, const int64_t *out_off,
                 const double *theta, const double *g_s, int32_t w, double *g_theta,
-                double *g_samples, int nthreads)
+                double *g_samples, double *g_theta_mag, double *g_samples_mag, uint8_t *rough,
+                uint8_t *samples_rough, int nthreads)
 {
     gset g = {samples, sample_off, trace_ptr, ns, half_offset, midpoint, central_x, dt};
     if (check_args(kind, &g, w, 1, 1, 1)) return 1;
@@ -465,11 +566,57 @@ int oracle_grad(int kind, const float *samples, const int64_t *sample_off, const
         theta_t th = {theta[3 * orow + 0], theta[3 * orow + 1], theta[3 * orow + 2]};
         if (kind == ORACLE_CMP) th.A = th.B = 0.0;
         double gA = 0.0, gB = 0.0, gq = 0.0;
+        double mA = 0.0, mB = 0.0, mq = 0.0;
         cell_t cl = eval_cell(&g, kind, c, ag, na, s, th, w, Ub);
         const double gs = g_s[orow];
+        const int is_rough = cl.kink || cl.fragile;
+        if (rough) rough[orow] = (uint8_t)is_rough;
+        const double t0 = s * dt;
+        const double xc = (kind == ORACLE_CRS) ? (double)central_x[c] : 0.0;
+        if (is_rough && samples_rough) {
+            /* every sample a window of this row could read, on any trace whose
+             * intersection exists, one sample of margin each side */
+            for (int p = 0; p < na; p++) {
+                const int gg = ag[p];
+                const int nsg = ns[gg];
+                for (int i = trace_ptr[gg]; i < trace_ptr[gg + 1]; i++) {
+                    const int64_t base = sample_off[gg] + (int64_t)(i - trace_ptr[gg]) * nsg;
+                    const double dm = (kind == ORACLE_CRS) ? (double)midpoint[i] - xc : 0.0;
+                    double mag;
+                    const double T = traveltime_sq(kind, t0, th, dm, half_offset[i], &mag);
+                    if (T < -FRAGILE_T_REL * mag) continue;
+                    const int64_t a = (int64_t)floor(sqrt(fmax(T, 0.0)) / dt) - hw;
+                    for (int64_t n = a - 1; n <= a + w + 1; n++)
+                        if (n >= 0 && n < nsg) samples_rough[base + n] = 1;
+                }
+            }
+        }
+        /* sum over contributing traces of |v_ij| per window sample j: the size
+         * of U_j before any cancellation (for the magnitudes below) */
+        double Ua[64];
+        double *Uab = (w <= 64) ? Ua : (double *)malloc(sizeof(double) * (size_t)w);
+        for (int jj = 0; jj < w; jj++) Uab[jj] = 0.0;
+        if (g_theta_mag || g_samples_mag) {
+            for (int p = 0; p < na; p++) {
+                const int gg = ag[p];
+                const int nsg = ns[gg];
+                for (int i = trace_ptr[gg]; i < trace_ptr[gg + 1]; i++) {
+                    const float *f = samples + sample_off[gg] + (int64_t)(i - trace_ptr[gg]) * nsg;
+                    const double dm = (kind == ORACLE_CRS) ? (double)midpoint[i] - xc : 0.0;
+                    double mag;
+                    const double T = traveltime_sq(kind, t0, th, dm, half_offset[i], &mag);
+                    if (T < 0.0) continue;
+                    const double tau = sqrt(T) / dt;
+                    if (!window_on_trace(tau, w, nsg)) continue;
+                    const double kf = floor(tau);
+                    const double x = tau - kf;
+                    const int64_t a = (int64_t)kf - hw;
+                    for (int jj = 0; jj < w; jj++)
+                        Uab[jj] += fabs(f[a + jj] + x * ((double)f[a + jj + 1] - f[a + jj]));
+                }
+            }
+        }
         if (cl.M > 0 && cl.D > 0.0 && gs != 0.0) {
-            const double t0 = s * dt;
-            const double xc = (kind == ORACLE_CRS) ? (double)central_x[c] : 0.0;
             const double MD = (double)cl.M * cl.D;
             for (int p = 0; p < na; p++) {
                 const int gg = ag[p];
@@ -487,17 +634,26 @@ int oracle_grad(int kind, const float *samples, const int64_t *sample_off, const
                     const double kf = floor(tau);
                     const double x = tau - kf;
                     const int64_t a = (int64_t)kf - hw;
-                    double dS_dtau = 0.0;
+                    double dS_dtau = 0.0, m_tau = 0.0;
                     for (int jj = 0; jj < w; jj++) {
                         const double f0 = f[a + jj], f1 = f[a + jj + 1];
                         const double v = f0 + x * (f1 - f0);
                         const double dS_dv = 2.0 * (Ub[jj] - cl.S * cl.M * v) / MD;
+                        /* its size before the subtraction cancels */
+                        const double m_dv = 2.0 * (Uab[jj] + cl.S * cl.M * fabs(v)) / MD;
                         dS_dtau += dS_dv * (f1 - f0);
+                        m_tau += m_dv * fabs(f1 - f0);
                         if (g_samples) {
 #pragma omp atomic
                             g_samples[base + a + jj] += gs * (1.0 - x) * dS_dv;
 #pragma omp atomic
                             g_samples[base + a + jj + 1] += gs * x * dS_dv;
+                        }
+                        if (g_samples_mag) {
+#pragma omp atomic
+                            g_samples_mag[base + a + jj] += fabs(gs) * (1.0 - x) * m_dv;
+#pragma omp atomic
+                            g_samples_mag[base + a + jj + 1] += fabs(gs) * x * m_dv;
                         }
                     }
                     if (T > 0.0) {
@@ -505,8 +661,11 @@ int oracle_grad(int kind, const float *samples, const int64_t *sample_off, const
                         if (kind == ORACLE_CRS) {
                             gA += dS_dtau * dtau_dT * 4.0 * dm * (t0 + 2.0 * th.A * dm);
                             gB += dS_dtau * dtau_dT * 2.0 * t0 * dm * dm;
+                            mA += m_tau * dtau_dT * 4.0 * fabs(dm) * (fabs(t0) + fabs(2.0 * th.A * dm));
+                            mB += m_tau * dtau_dT * 2.0 * t0 * dm * dm;
                         }
                         gq += dS_dtau * dtau_dT * h * h;
+                        mq += m_tau * dtau_dT * h * h;
                     }
                 }
             }
@@ -514,6 +673,12 @@ int oracle_grad(int kind, const float *samples, const int64_t *sample_off, const
         g_theta[3 * orow + 0] = gs * gA;
         g_theta[3 * orow + 1] = gs * gB;
         g_theta[3 * orow + 2] = gs * gq;
+        if (g_theta_mag) {
+            g_theta_mag[3 * orow + 0] = fabs(gs) * mA;
+            g_theta_mag[3 * orow + 1] = fabs(gs) * mB;
+            g_theta_mag[3 * orow + 2] = fabs(gs) * mq;
+        }
+        if (Uab != Ua) free(Uab);
         if (Ub != U) free(Ub);
     }
     free(rows);

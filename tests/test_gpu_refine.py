@@ -168,17 +168,11 @@ def test_autograd_wrapper_matches_oracle_gradient():
     weights = torch.from_numpy(rng.uniform(0.5, 1.5, jobs.n_out).astype(np.float32)).cuda()
     (S * weights).sum().backward()
     torch.cuda.synchronize()
-    gt_ref, gsm_ref = oracle.grad("crs", gs, jobs, th.astype(np.float64), weights.cpu().numpy().astype(np.float64),
-                                  wl.w)
     S_ref, _, _, fr = oracle.point("crs", gs, jobs, th.astype(np.float64), wl.w)
     assert np.abs(S.detach().cpu().numpy() - S_ref)[~fr].max() <= gu.S_TOL
     gt = theta.grad.cpu().numpy().astype(np.float64)
-    for k in range(3):
-        ref = gt_ref[~fr, k]
-        err = np.abs(gt[~fr, k] - ref) / (np.abs(ref) + 1e-3 * np.abs(ref).max() + 1e-30)
-        assert float(np.median(err)) < 1e-5 and float((err > 1e-3).mean()) < 0.01, k
     gsm = samples.grad.cpu().numpy().astype(np.float64)
-    assert np.linalg.norm(gsm - gsm_ref) / np.linalg.norm(gsm_ref) < 1e-3
+    _say("autograd", gu.assert_grad_parity("autograd", "crs", gs, jobs, th, weights.cpu().numpy(), wl.w, gt, gsm))
 
 
 def _peaks_ref(P, nA, nB, nq, K):

@@ -82,8 +82,7 @@ def test_ragged_cmp(w):
     grid = synth.Grid(q=synth.velocity_grid(700, 3000, 13))
     gpu = gu.run_scan("cmp", gs, jobs, grid, w, panel=True)
     ref = oracle.scan("cmp", gs, jobs, grid, w, panel=True)
-    _say("ragged cmp", w, gu.compare(f"ragged cmp w={w}", gpu, ref, gu.sample_scale(gs, jobs),
-                                     s_tol=gu.s_tol(w)))
+    _say("ragged cmp", w, gu.compare(f"ragged cmp w={w}", gpu, ref, gu.sample_scale(gs, jobs)))
 
 
 @pytest.mark.parametrize("w", [1, 5, 9, 11, 15])
@@ -98,8 +97,7 @@ def test_ragged_crs_with_negative_radicands(w):
                       q=synth.velocity_grid(700, 3000, 5))
     gpu = gu.run_scan("crs", gs, jobs, grid, w, panel=True)
     ref = oracle.scan("crs", gs, jobs, grid, w, panel=True)
-    _say("ragged crs", w, gu.compare(f"ragged crs w={w}", gpu, ref, gu.sample_scale(gs, jobs),
-                                     s_tol=gu.s_tol(w)))
+    _say("ragged crs", w, gu.compare(f"ragged crs w={w}", gpu, ref, gu.sample_scale(gs, jobs)))
 
 
 def test_max_ns_and_tiny_traces():
@@ -178,6 +176,9 @@ def test_point_evaluation(kind):
 
 @pytest.mark.parametrize("kind", ["cmp", "crs"])
 def test_gradient_matches_oracle(kind):
+    """dL/dtheta on every row and dL/dsample on every sample against the
+    oracle's FP64 gradient, each within K_GRAD 2^-24 of the magnitude of its
+    terms (tests/gpu_util.py); rows the oracle flags as kinks are excluded."""
     import torch
     import paper_1907_11678_amd as semb
     wl = synth.cmp_plain(ids=[5]) if kind == "cmp" else synth.crs_line(centrals=[70])
@@ -191,22 +192,9 @@ def test_gradient_matches_oracle(kind):
     semb.semblance_grad(dg, dj, 0 if kind == "cmp" else 1, torch.from_numpy(th).cuda(),
                         torch.from_numpy(g_s).cuda(), wl.w, g_theta, g_smp)
     torch.cuda.synchronize()
-    gt_ref, gsm_ref = oracle.grad(kind, gs, jobs, th.astype(np.float64), g_s.astype(np.float64), wl.w)
-    _, _, _, fr = oracle.point(kind, gs, jobs, th.astype(np.float64), wl.w)
     gt = g_theta.cpu().numpy().astype(np.float64)
-    comps = [2] if kind == "cmp" else [0, 1, 2]
-    for k in comps:
-        ref = gt_ref[~fr, k]
-        got = gt[~fr, k]
-        err = np.abs(got - ref) / (np.abs(ref) + 1e-3 * np.abs(ref).max() + 1e-30)
-        # a window whose intersection lies within FP32 rounding of a sample uses the
-        # neighbouring interpolation segment, whose slope differs: allow rare rows
-        frac_bad = float((err > 1e-3).mean())
-        assert frac_bad < 0.01, (k, frac_bad, float(np.median(err)))
-        assert float(np.median(err)) < 1e-5, (k, float(np.median(err)))
     gsm = g_smp.cpu().numpy().astype(np.float64)
-    rel = np.linalg.norm(gsm - gsm_ref) / np.linalg.norm(gsm_ref)
-    assert rel < 1e-3, rel
+    _say("gradient", kind, gu.assert_grad_parity(f"gradient {kind}", kind, gs, jobs, th, g_s, wl.w, gt, gsm))
     # autograd accumulation: a second call adds the same amount again
     semb.semblance_grad(dg, dj, 0 if kind == "cmp" else 1, torch.from_numpy(th).cuda(),
                         torch.from_numpy(g_s).cuda(), wl.w, g_theta, g_smp)

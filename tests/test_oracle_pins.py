@@ -223,6 +223,18 @@ def _tiny_line(seed):
     return gs
 
 
+def _gap_vs_panel(gap, panel, name):
+    """The oracle's gap is the best S minus the second-best S of any other
+    parameter (equal values count twice, so a tie gives 0), from a panel the
+    brute force computed; infinite with a single parameter."""
+    if panel.shape[1] == 1:
+        return [] if np.isinf(gap).all() else [f"{name}: gap of a one-parameter grid is not infinite"]
+    top = np.sort(panel, axis=1)
+    want = top[:, -1] - top[:, -2]
+    err = np.abs(gap - want).max(initial=0.0)
+    return [f"{name}: gap differs from the brute force's top two by {err}"] if err > 1e-12 else []
+
+
 def pin_brute_force(lib=None, seeds=(0, 1, 2)):
     bad = []
     for seed in seeds:
@@ -235,6 +247,7 @@ def pin_brute_force(lib=None, seeds=(0, 1, 2)):
             bb, bs, bst, bp = helpers.brute_scan("cmp", gs, jobs, grid, w)
             if np.abs(r.panel - bp).max() > 1e-12:
                 bad.append(f"brute CMP seed {seed} w {w}: panel differs by {np.abs(r.panel - bp).max()}")
+            bad += _gap_vs_panel(r.gap, bp, f"brute CMP seed {seed} w {w}")
             big = r.gap > 1e-9
             if (r.best[big] != bb[big]).any() or np.abs(r.stack - bst).max() > 1e-12:
                 bad.append(f"brute CMP seed {seed} w {w}: pick or stack differs")
@@ -248,6 +261,7 @@ def pin_brute_force(lib=None, seeds=(0, 1, 2)):
             bb, bs, bst, bp = helpers.brute_scan("crs", gs, jobs, grid, w)
             if np.abs(r.panel - bp).max() > 1e-12:
                 bad.append(f"brute CRS seed {seed} w {w}: panel differs by {np.abs(r.panel - bp).max()}")
+            bad += _gap_vs_panel(r.gap, bp, f"brute CRS seed {seed} w {w}")
             big = r.gap > 1e-9
             if (r.best[big] != bb[big]).any() or np.abs(r.stack - bst).max() > 1e-12:
                 bad.append(f"brute CRS seed {seed} w {w}: pick or stack differs")
@@ -287,10 +301,14 @@ def pin_gradient_fd(lib=None):
     w = 9
     ns = jobs.n_out
     g_s = np.random.default_rng(2).uniform(0.5, 1.5, ns)
-    gt, gsm = oracle.grad("crs", gs, jobs, theta, g_s, w, library=lib)
+    gt, gsm, det = oracle.grad("crs", gs, jobs, theta, g_s, w, library=lib, detail=True)
     S0, _, M, _ = oracle.point("crs", gs, jobs, theta, w, library=lib)
+    # the steps move every intersection by less than the oracle's default kink
+    # band of 1e-4 samples, so only rows it flags as rough can see a kink
     steps = np.array([5e-5, 1e-8, 4e-8]) * 1e-4
-    rows = [r for r in range(40, ns - 20, 3) if M[r] > 0 and S0[r] > 0.05]
+    rows = [r for r in range(40, ns - 20, 3) if M[r] > 0 and S0[r] > 0.05 and not det.rough[r]]
+    if len(rows) < 60:
+        bad.append(f"gradient FD: only {len(rows)} smooth rows to check")
     for k in range(3):
         tp, tm = theta.copy(), theta.copy()
         tp[:, k] += steps[k]
@@ -305,9 +323,7 @@ def pin_gradient_fd(lib=None):
             scale = abs(fd[r]) + abs(gt[r, k]) + 1e-30
             if abs(fd[r] - gt[r, k]) > 1e-4 * scale + 1e-9 * abs(g_s[r] / steps[k]) * 1e-6:
                 nerr += 1
-        # a step that crosses a sample boundary (a kink of the interpolant) can
-        # spoil an isolated row; require agreement almost everywhere
-        if nerr > max(1, len(rows) // 50):
+        if nerr:
             bad.append(f"gradient FD component {k}: {nerr} of {len(rows)} rows disagree")
     # samples: a handful of single-sample perturbations
     rng = np.random.default_rng(4)
@@ -350,6 +366,136 @@ def pin_crs_reduces_to_cmp(lib=None):
     cr = oracle.scan("crs", gs, synth.line_crs_jobs(gs, [2], 0), grid, 3, panel=True, library=lib)
     if not np.array_equal(cm.panel, cr.panel):
         bad.append("CRS(A=B=0) over {c} differs from CMP")
+    return bad
+
+
+def pin_scan_rows(lib=None):
+    """oracle_scan_rows on a shuffled subset of rows equals oracle_scan on the
+    same rows in every output, for CMP and for CRS with nA != nB != nq (a slip
+    in decoding the flat index into (iA, iB, iq) changes the picks)."""
+    bad = []
+    gs = _tiny_line(5)
+    rng = np.random.default_rng(13)
+    cases = [("cmp", synth.cmp_jobs(gs), synth.Grid(q=synth.velocity_grid(600, 2400, 7)), 3),
+             ("crs", synth.line_crs_jobs(gs, [1, 2, 3], 1),
+              synth.Grid(A=np.array([-3e-3, -1e-3, 0.0, 2e-3], np.float32),
+                         B=np.array([-3e-5, 1e-5], np.float32),
+                         q=synth.velocity_grid(600, 2400, 3)), 5)]
+    for kind, jobs, grid, w in cases:
+        full = oracle.scan(kind, gs, jobs, grid, w, library=lib)
+        rj = np.concatenate([np.full(int(gs.ns[c]), j) for j, c in enumerate(jobs.central)]).astype(np.int32)
+        rs = np.concatenate([np.arange(int(gs.ns[c])) for c in jobs.central]).astype(np.int32)
+        pick = rng.permutation(rj.size)[: max(1, rj.size * 2 // 3)]
+        r = oracle.scan_rows(kind, gs, jobs, grid, w, rj[pick], rs[pick], library=lib)
+        rows = jobs.out_off[rj[pick]] + rs[pick]
+        for name in ("best", "s_best", "stack", "gap", "fragile", "cond"):
+            if not np.array_equal(getattr(r, name), getattr(full, name)[rows]):
+                bad.append(f"scan_rows {kind}: {name} differs from the full scan")
+    return bad
+
+
+def pin_condition_number(lib=None):
+    """kappa (the oracle's per-cell condition number of S) bounds the
+    first-order change of S when every sample moves by a relative delta, and
+    for one trace with a one-sample window (S = 1 whenever v != 0) it has the
+    closed form 4 (|f[k]| + |f[k+1]|) / |v|."""
+    bad = []
+    rng = np.random.default_rng(31)
+    for w in (1, 5):
+        gs = helpers.random_line(rng, 3, fold_range=(2, 4), ns_range=(40, 60), hmax=300.0, smooth=True)
+        jobs = synth.line_crs_jobs(gs, [1], 1)
+        grid = synth.Grid(A=np.array([-1e-3, 1e-3], np.float32), B=np.zeros(1, np.float32),
+                          q=synth.velocity_grid(800, 2400, 3))
+        r = oracle.scan("crs", gs, jobs, grid, w, panel=True, library=lib)
+        sgn = np.where(rng.random(gs.samples.size) < 0.5, -1.0, 1.0)
+        pert = (gs.samples.astype(np.float64) * (1.0 + 1e-6 * sgn)).astype(np.float32)
+        nz = gs.samples != 0
+        delta = float(np.abs((pert[nz].astype(np.float64) - gs.samples[nz]) / gs.samples[nz]).max())
+        gp = synth.Gathers(pert, gs.sample_off, gs.trace_ptr, gs.ns, gs.half_offset, gs.midpoint,
+                           gs.central_x, gs.dt)
+        rp = oracle.scan("crs", gp, jobs, grid, w, panel=True, library=lib)
+        excess = np.abs(rp.panel - r.panel) - (delta * r.panel_cond * 1.01 + 1e-12)
+        if excess.max() > 0:
+            bad.append(f"kappa w {w}: a relative {delta:.3g} perturbation moved S beyond delta kappa")
+    ns = 30
+    f = rng.standard_normal((1, ns)).astype(np.float32)
+    g1 = synth.pack_gathers([f], [np.array([40.0], np.float32)], [np.zeros(1)], [0.0], 0.004)
+    q = np.array([4.0 / 1900.0 ** 2], np.float32)
+    r = oracle.scan("cmp", g1, synth.cmp_jobs(g1), synth.Grid(q=q), 1, library=lib)
+    dt1 = float(g1.dt)
+    for s in range(ns):
+        tau = math.sqrt((s * dt1) ** 2 + float(q[0]) * 40.0 ** 2) / dt1
+        k = math.floor(tau)
+        if k + 1 > ns - 1:
+            continue
+        f0, f1 = float(f[0, k]), float(f[0, k + 1])
+        v = f0 + (tau - k) * (f1 - f0)
+        want = 4.0 * (abs(f0) + abs(f1)) / abs(v)
+        if abs(r.cond[s] - want) > 1e-9 * want:
+            bad.append(f"kappa of one trace, w = 1, s = {s}: {r.cond[s]} != {want}")
+            break
+    return bad
+
+
+def pin_gradient_magnitudes(lib=None):
+    """The magnitude sums bound the gradients (|g| <= mag, term by term), and
+    the rough flag marks exactly the rows with a contributing intersection
+    within the kink band of an integer: one trace at h = 0 has tau = s (every
+    row rough); at h > 0 the flag follows the fraction of tau."""
+    bad = []
+    gs, jobs, theta = _grad_case()
+    g_s = np.random.default_rng(6).uniform(-1.5, 1.5, jobs.n_out)
+    gt, gsm, d = oracle.grad("crs", gs, jobs, theta, g_s, 9, library=lib, detail=True)
+    if (np.abs(gt) > d.g_theta_mag * (1 + 1e-12) + 1e-300).any():
+        bad.append("gradient magnitudes: |dL/dtheta| exceeds its magnitude sum")
+    if (np.abs(gsm) > d.g_samples_mag * (1 + 1e-12) + 1e-300).any():
+        bad.append("gradient magnitudes: |dL/dsample| exceeds its magnitude sum")
+    if not (d.g_theta_mag[:, 2] > 0).mean() > 0.9:
+        bad.append("gradient magnitudes: dL/dq magnitudes missing")
+    rng = np.random.default_rng(8)
+    ns, dt = 40, 0.004
+    f = rng.standard_normal((3, ns)).astype(np.float32)
+    h = np.array([0.0, 0.0, 0.0], np.float32)
+    g0 = synth.pack_gathers([f], [h], [np.zeros(3)], [0.0], dt)
+    j0 = synth.cmp_jobs(g0)
+    th = np.zeros((ns, 3))
+    th[:, 2] = 4.0 / 2000.0 ** 2
+    _, _, d0 = oracle.grad("cmp", g0, j0, th, np.ones(ns), 3, library=lib, detail=True)
+    if not d0.rough[1:ns - 2].all():
+        bad.append("rough flag: tau = s exactly (h = 0) not flagged")
+    hv = np.float32(900.0)
+    g1 = synth.pack_gathers([f[:1]], [np.array([hv])], [np.zeros(1)], [0.0], dt)
+    j1 = synth.cmp_jobs(g1)
+    for qv, s in ((4.0 / 2000.0 ** 2, 20), (4.0 / 2500.0 ** 2, 25)):
+        th = np.zeros((ns, 3))
+        th[:, 2] = qv
+        _, _, d1 = oracle.grad("cmp", g1, j1, th, np.ones(ns), 1, library=lib, detail=True)
+        dtg = float(g1.dt)
+        for r in range(ns):
+            tau = math.sqrt((r * dtg) ** 2 + qv * float(hv) ** 2) / dtg
+            k = math.floor(tau)
+            if k + 1 > ns - 1:
+                continue
+            x = tau - k
+            want = x < oracle.KINK_DEFAULT or x > 1.0 - oracle.KINK_DEFAULT
+            if bool(d1.rough[r]) != want:
+                bad.append(f"rough flag at tau {tau:.9f}: {bool(d1.rough[r])} != {want}")
+                break
+    # intersections placed 3e-5 below and above an integer (further than the
+    # float32 rounding of h can move them) are both kinks
+    for c in (-3e-5, 3e-5):
+        tau_t = 20.0 + c
+        hh = np.float32(math.sqrt(max(tau_t ** 2 - 10.0 ** 2, 0.0)) * dt / math.sqrt(4.0 / 2000.0 ** 2))
+        g2 = synth.pack_gathers([f[:1]], [np.array([hh])], [np.zeros(1)], [0.0], dt)
+        th = np.zeros((ns, 3))
+        th[:, 2] = 4.0 / 2000.0 ** 2
+        _, _, d2 = oracle.grad("cmp", g2, synth.cmp_jobs(g2), th, np.ones(ns), 1, library=lib, detail=True)
+        dtg = float(g2.dt)
+        tau = math.sqrt((10 * dtg) ** 2 + th[10, 2] * float(hh) ** 2) / dtg
+        if not (abs(tau - 20.0) < 1e-4 and (tau - 20.0) * c > 0):
+            bad.append(f"rough flag case: tau {tau:.9f} not on the intended side of 20")
+        elif not d2.rough[10]:
+            bad.append(f"rough flag: tau {tau:.9f} next to an integer not flagged")
     return bad
 
 
@@ -413,7 +559,8 @@ def pin_corrected(lib=None):
 
 PINS = [pin_hand_cases, pin_zero_moveout_closed_form, pin_ramp_traces, pin_aligned_ricker_cmp,
         pin_aligned_ricker_crs, pin_tie_break, pin_brute_force, pin_gradient_fd,
-        pin_crs_reduces_to_cmp, pin_corrected]
+        pin_crs_reduces_to_cmp, pin_scan_rows, pin_condition_number, pin_gradient_magnitudes,
+        pin_corrected]
 
 
 # --------------------------------------------------------------------------
@@ -498,8 +645,8 @@ MUTATIONS = [
      "const double v = f0 + x * (f0 - f1);\n                U[j]"),
     ("interpolation index", "const double f0 = f[a + j], f1 = f[a + j + 1];\n            "
      "    const double v", "const double f0 = f[a + j], f1 = f[a + j + 2];\n                const double v"),
-    ("window start off by one", "const int64_t a = (int64_t)kf - hw;\n            for (int j",
-     "const int64_t a = (int64_t)kf - hw + 1;\n            for (int j"),
+    ("window start off by one", "const int64_t a = (int64_t)kf - hw;\n            /* a kink",
+     "const int64_t a = (int64_t)kf - hw + 1;\n            /* a kink"),
     ("dropped curvature term", "return y * y + b + c;", "return y * y + c;"),
     ("dip factor", "double y = t0 + 2.0 * th.A * dm;", "double y = t0 + th.A * dm;"),
     ("transposed offset and displacement", "double c = th.q * h * h;", "double c = th.q * dm * dm;"),
@@ -513,6 +660,18 @@ MUTATIONS = [
     ("sample-gradient weight", "g_samples[base + a + jj] += gs * (1.0 - x) * dS_dv;",
      "g_samples[base + a + jj] += gs * x * dS_dv;"),
     ("dtau/dT", "1.0 / (2.0 * dt * sqrt(T))", "1.0 / (dt * sqrt(T))"),
+    ("runner-up dropped", "s2 = s1;\n                        s1 = cl.S;", "s1 = cl.S;"),
+    ("scan_rows runner-up dropped", "s2 = s1;\n                s1 = cl.S;", "s1 = cl.S;"),
+    ("scan_rows B decode", "            th.B = (kind == ORACLE_CRS) ? (double)B[(p / nq) % nB] : 0.0;",
+     "            th.B = (kind == ORACLE_CRS) ? (double)B[(p / nq) % nA] : 0.0;"),
+    ("scan_rows A decode", "            th.A = (kind == ORACLE_CRS) ? (double)A[p / ((int64_t)nq * nB)] : 0.0;",
+     "            th.A = (kind == ORACLE_CRS) ? (double)A[p / ((int64_t)nq * nA)] : 0.0;"),
+    ("kappa energy factor", "kappa += cl.S / cl.D * 2.0 * sqrt(Di)", "kappa += cl.S / cl.D * sqrt(Di)"),
+    ("kappa window-sum factor", "kappa += fabs(2.0 * U[j] / MD)", "kappa += fabs(U[j] / MD)"),
+    ("gradient magnitude sign", "m_tau += m_dv * fabs(f1 - f0);", "m_tau += m_dv * (f1 - f0);"),
+    ("sample magnitude weight", "g_samples_mag[base + a + jj + 1] += fabs(gs) * x * m_dv;",
+     "g_samples_mag[base + a + jj + 1] += 0.0 * m_dv;"),
+    ("kink band one-sided", "if (x < KINK_TAU || x > 1.0 - KINK_TAU) c.kink = 1;", "if (x < KINK_TAU) c.kink = 1;"),
 ]
 
 

@@ -1,6 +1,6 @@
 """Property-based search (hypothesis) over tiny random cases: the FP64 oracle
 must equal the independent brute-force evaluation of Eq. (1) in
-tests/helpers.py on every panel cell, whatever the fold, trace lengths,
+tests/helpers.py on every panel cell (and in the top-two gap), whatever the fold, trace lengths,
 windows, offsets, CRS dips and curvatures (negative radicands included),
 all-zero traces and window positions at the trace ends."""
 from __future__ import annotations
@@ -61,3 +61,16 @@ def test_oracle_equals_brute_force(case):
         assert (S[rows, r.best] >= S.max(axis=1) - 1e-12).all()
         assert np.array_equal(r.best, np.argmax(r.panel, axis=1))
         assert np.abs(r.stack - ST[rows, r.best]).max() <= 1e-12
+        # gap: best minus second-best S over the brute force's panel
+        if S.shape[1] > 1:
+            top = np.sort(S, axis=1)
+            assert np.abs(r.gap - (top[:, -1] - top[:, -2])).max() <= 1e-12
+        else:
+            assert np.isinf(r.gap).all()
+        # the row-subset scan reproduces the full scan on every row it is given
+        rj = np.concatenate([np.full(int(gs.ns[c]), j) for j, c in enumerate(jobs.central)]).astype(np.int32)
+        rs = np.concatenate([np.arange(int(gs.ns[c])) for c in jobs.central]).astype(np.int32)
+        rr = oracle.scan_rows(kind, gs, jobs, grid, w, rj[::-1], rs[::-1])
+        out = jobs.out_off[rj[::-1]] + rs[::-1]
+        for name in ("best", "s_best", "stack", "gap", "fragile"):
+            assert np.array_equal(getattr(rr, name), getattr(r, name)[out]), name
