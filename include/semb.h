@@ -104,7 +104,13 @@ typedef struct semb_jobs {
     const int64_t *out_off;      /* [njobs]                                           */
     int32_t njobs;               /* [host] >= 0                                       */
     int32_t max_apert;           /* [host] upper bound of gathers per aperture
-                                    (1 for CMP), 1 .. SEMB_APERT_LIMIT                */
+                                    (1 for CMP), 1 .. SEMB_APERT_LIMIT.  A CRS job
+                                    whose aperture lists more gathers is not
+                                    computed by any call: its rows get the marker
+                                    best = -1, s_best = -1, stack = 0 (panel cells
+                                    -1; stack and semb_refine: S = -1, stack = 0,
+                                    theta kept; semblance_grad: zero gradient;
+                                    corrected gathers: zeros).                         */
     int64_t n_out;               /* [host] number of output rows (>= every
                                     out_off[j] + ns[central[j]])                      */
 } semb_jobs;

@@ -642,8 +642,9 @@ def _semblance_at_class():
             if samples.data_ptr() != g.samples.data_ptr():
                 raise ValueError("samples must be the tensor the gathers were uploaded with")
             theta = theta.contiguous()
-            S = torch.empty(jobs.n_out, dtype=torch.float32, device=theta.device)
-            st = torch.empty_like(S)
+            # zeros: rows that no job covers (gaps between out_off ranges) stay 0
+            S = torch.zeros(jobs.n_out, dtype=torch.float32, device=theta.device)
+            st = torch.zeros_like(S)
             stack(g, jobs, kind, theta, w, S, st)
             ctx.save_for_backward(theta)
             ctx.g, ctx.jobs, ctx.kind, ctx.w = g, jobs, kind, w
@@ -653,7 +654,7 @@ def _semblance_at_class():
         @staticmethod
         def backward(ctx, gS, _gst):
             (theta,) = ctx.saved_tensors
-            g_theta = torch.empty_like(theta)
+            g_theta = torch.zeros_like(theta)
             g_samples = torch.zeros_like(ctx.g.samples) if ctx.needs_input_grad[0] else None
             semblance_grad(ctx.g, ctx.jobs, ctx.kind, theta, gS.contiguous().float(), ctx.w, g_theta, g_samples)
             return g_samples, g_theta, None, None, None, None

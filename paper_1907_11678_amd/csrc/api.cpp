@@ -157,6 +157,7 @@ semb::JobView job_view(const semb_jobs *jobs, const semb_gathers *g, bool crs)
     v.out_off = jobs->out_off;
     v.njobs = jobs->njobs;
     v.n_sblk = (g->ns_max + 63) / 64;
+    v.max_apert = jobs->max_apert;
     return v;
 }
 
@@ -290,6 +291,7 @@ semb_status point_common(bool grad, const semb_gathers *g, const semb_jobs *jobs
     a.out_off = jobs->out_off;
     a.njobs = jobs->njobs;
     a.n_sblk = (g->ns_max + 63) / 64;
+    a.max_apert = jobs->max_apert;
     a.theta = theta;
     a.g_s = g_s;
     a.s_out = s_out;
@@ -359,6 +361,12 @@ int64_t semb_batch_plan(const semb_batch_host *h, int32_t split_params, semb_til
             return -1;
         }
         int64_t ntr = 0;
+        if (crs && (h->apert_ptr[j + 1] - h->apert_ptr[j] < 0 ||
+                    h->apert_ptr[j + 1] - h->apert_ptr[j] > SEMB_APERT_LIMIT)) {
+            fail(SEMB_EINVAL, "semb_batch_plan: job %d lists %d aperture gathers (1..%d allowed)", j,
+                 h->apert_ptr[j + 1] - h->apert_ptr[j], SEMB_APERT_LIMIT);
+            return -1;
+        }
         if (crs) {
             for (int32_t k = h->apert_ptr[j]; k < h->apert_ptr[j + 1]; ++k) {
                 const int32_t gg = h->apert_gather[k];
@@ -556,6 +564,7 @@ semb_status semb_refine(const semb_gathers *g, const semb_jobs *jobs, int32_t ki
     a.out_off = jobs->out_off;
     a.njobs = jobs->njobs;
     a.n_sblk = (g->ns_max + 63) / 64;
+    a.max_apert = jobs->max_apert;
     a.theta = theta;
     a.s_out = s_out;
     a.stack_out = stack_out;
@@ -648,6 +657,7 @@ semb_status semb_corrected_gathers(const semb_gathers *g, const semb_jobs *jobs,
     a.out_off = jobs->out_off;
     a.njobs = jobs->njobs;
     a.n_sblk = (g->ns_max + 63) / 64;
+    a.max_apert = jobs->max_apert;
     a.theta = theta;
     a.w = 1;
     return hip_status(semb::launch_corrected(kind, a, corr_off, out, stream), "semb_corrected_gathers launch");
@@ -744,6 +754,9 @@ semb_status semb_tune_scan(const semb_gathers *g, const semb_jobs *jobs, int32_t
     TRY(hip_status(hipMemcpyAsync(nsv.data(), g->ns, sizeof(int32_t) * g->ngathers, hipMemcpyDeviceToHost, stream),
                    "semb_tune_scan: copy"));
     TRY(hip_status(hipStreamSynchronize(stream), "semb_tune_scan: synchronize"));
+    for (int j = 0; j < sub.njobs; ++j)
+        if (cen[j] < 0 || cen[j] >= g->ngathers)
+            return fail(SEMB_EINVAL, "semb_tune_scan: job %d has central gather %d out of range", j, cen[j]);
     size_t nrows = 0;
     for (int j = 0; j < sub.njobs; ++j) nrows += (size_t)std::max(0, nsv[cen[j]]);
     // one copy per array when the sampled rows are (nearly) contiguous

@@ -31,7 +31,16 @@ struct JobView {
     const int64_t *out_off;
     int32_t njobs;
     int32_t n_sblk;
+    int32_t max_apert;  // the caller's bound on gathers per aperture (<= SEMB_APERT_LIMIT)
 };
+
+// Does job `job`'s aperture list more gathers than the caller declared?  Such a
+// job is not computed by any kernel; its rows get the marker the ABI documents
+// (scan: best = -1, s_best = -1, stack = 0; point evaluation: S = -1).
+__device__ __forceinline__ bool apert_over(const int32_t *apert_ptr, int32_t max_apert, int job)
+{
+    return apert_ptr != nullptr && apert_ptr[job + 1] - apert_ptr[job] > max_apert;
+}
 
 // One parameter grid (flat index (iA * nB + iB) * nq + iq) with the window
 // and the window-energy planes for that window (workspace, one per sample).
@@ -96,6 +105,7 @@ struct PointArgs {
     const int64_t *out_off;
     int32_t njobs;
     int32_t n_sblk;
+    int32_t max_apert;
     const float *theta;   // [n_out][3]
     const float *g_s;     // [n_out] (gradient only)
     float *s_out;

@@ -222,6 +222,15 @@ point_kernel(PointArgs a)
     int job, s;
     const int64_t row = my_row<KIND>(a, job, s);
     if (row < 0) return;
+    if (KIND == SEMB_KIND_CRS && apert_over(a.apert_ptr, a.max_apert, job)) {  // the documented marker
+        if (!GRAD) {
+            a.s_out[row] = -1.f;
+            a.stack_out[row] = 0.f;
+        } else {
+            a.g_theta[3 * row + 0] = a.g_theta[3 * row + 1] = a.g_theta[3 * row + 2] = 0.f;
+        }
+        return;
+    }
     const RowCtx r = row_ctx<KIND>(a, job);
     const double A = (KIND == SEMB_KIND_CRS) ? (double)a.theta[3 * row + 0] : 0.0;
     const double B = (KIND == SEMB_KIND_CRS) ? (double)a.theta[3 * row + 1] : 0.0;
@@ -252,6 +261,11 @@ refine_kernel(PointArgs a, RefineArgs o)
     int job, s;
     const int64_t row = my_row<KIND>(a, job, s);
     if (row < 0) return;
+    if (KIND == SEMB_KIND_CRS && apert_over(a.apert_ptr, a.max_apert, job)) {  // theta left as given
+        a.s_out[row] = -1.f;
+        a.stack_out[row] = 0.f;
+        return;
+    }
     const RowCtx r = row_ctx<KIND>(a, job);
     float th[3] = {o.theta[3 * row + 0], o.theta[3 * row + 1], o.theta[3 * row + 2]};
     if (KIND == SEMB_KIND_CMP) th[0] = th[1] = 0.f;
@@ -322,12 +336,18 @@ corrected_kernel(PointArgs a, const int64_t *__restrict__ corr_off, float *__res
     const double A = (KIND == SEMB_KIND_CRS) ? (double)a.theta[3 * row + 0] : 0.0;
     const double B = (KIND == SEMB_KIND_CRS) ? (double)a.theta[3 * row + 1] : 0.0;
     const double q = (double)a.theta[3 * row + 2];
+    // an aperture longer than the caller declared: every corrected value is 0
+    const bool over = KIND == SEMB_KIND_CRS && apert_over(a.apert_ptr, a.max_apert, job);
     float *o = out + corr_off[job] + s;
     for (int k = r.k0; k < r.k1; ++k) {
         const int g = r.ag ? r.ag[k] : r.c;
         const int nsg = a.ns[g];
         const int tb = a.trace_ptr[g], te = a.trace_ptr[g + 1];
         for (int i = tb; i < te; ++i, o += nsc) {
+            if (over) {
+                *o = 0.f;
+                continue;
+            }
             const float dmf = (KIND == SEMB_KIND_CRS) ? (float)((double)a.midpoint[i] - r.xc) : 0.f;
             const Isect hit = intersect<KIND, 1>(s, A, B, q, a.half_offset[i], dmf, r.inv_dt, nsg);
             float v = 0.f;

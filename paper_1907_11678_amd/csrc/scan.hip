@@ -144,6 +144,12 @@ batch_kernel(BatchArgs b)
         if (tl.nsplit > 1 && (tl.group < 0 || tl.group >= b.ngroups || tl.split < 0 || tl.split >= tl.nsplit ||
                               tl.part_base < 0 || (int64_t)tl.part_base + tl.nsplit > b.nparts))
             continue;
+        if (kind == SEMB_KIND_CRS && apert_over(b.j.apert_ptr, b.j.max_apert, tl.job)) {
+            // every split of the group writes the same marker rows
+            write_apert_marker(b.j, tl.job, tl.sblk, b.g.ns[b.j.central[tl.job]], b.pr.npar, b.best, b.s_best,
+                               b.stack, nullptr, nullptr);
+            continue;
+        }
         float bS, bSt;
         int bI;
         if (kind == SEMB_KIND_CMP)

@@ -135,10 +135,20 @@ struct __align__(16) TraceRun {
     double cc;
 };
 
+// Positions of one LDS plane: a block of zeros (W + 1 words, rounded up to
+// 4) that windows off their trace read in the branch-free tile shapes, then
+// the CAP staged positions.
+template <int W, int CAP>
+struct Plane {
+    static constexpr int ZP = (W + 1 + 3) & ~3;  // words of the zero block, at position 0
+    static constexpr int STRIDE = ZP + CAP;      // words per plane
+};
+
 template <int KIND, int W, int P, int NW, int CAP, int TMAX>
 struct StageLds {
-    float st[4][CAP];                               // staged samples, then their window energy
-                                                    // (Gram form): u0, u1, u2^2
+    float st[4][Plane<W, CAP>::STRIDE];             // staged samples, then their window energy
+                                                    // (Gram form): u0, u1, u2^2; each plane
+                                                    // starts with the zero block
     double2 tab[KIND == SEMB_KIND_CRS ? NW * P : 1][WAVE];  // CRS: (2 alpha + beta, alpha^2 + gamma)
     // the traces of the current part: fixed per tile ...
     long long t_base[TMAX];                         // element of the trace's sample 0
@@ -208,13 +218,18 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
 
     __syncthreads();  // the previous tile (persistent loop) is done with L
     // ---- the job's aperture: gathers and cumulative trace counts ----------
+    // (a CRS aperture longer than jv.max_apert never reaches this point: the
+    // kernels write the documented marker instead, see apert_over)
     int na = 1, afirst = -1;
     if (CRS && jv.apert_ptr != nullptr) {
         afirst = jv.apert_ptr[job];
-        na = min(jv.apert_ptr[job + 1] - afirst, SEMB_APERT_LIMIT);
-        na = max(na, 0);
+        na = max(min(jv.apert_ptr[job + 1] - afirst, jv.max_apert), 0);
     }
     if (tid < na) L.ag_s[tid] = (afirst < 0) ? c : jv.apert_gather[afirst + tid];
+    // the zero block at the start of every plane (read by off-trace windows;
+    // the previous tile's pick may have reused it)
+    constexpr int ZW = Plane<W, CAP>::ZP;
+    if (tid < 4 * ZW) L.st[tid / ZW][tid % ZW] = 0.f;
     __syncthreads();
     if (tid == 0) {
         int acc = 0;
@@ -354,7 +369,7 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                     len = min(len, CAP);
                     incl = len;
                 }
-                if (wv == 0 && lane < nfit) L.run[e].off = incl - len - L.t_lo[e];
+                if (wv == 0 && lane < nfit) L.run[e].off = Plane<W, CAP>::ZP + incl - len - L.t_lo[e];
 
                 // ---- stage the samples and their window energy -------------------
                 // Direct global->LDS loads (global_load_lds_dword): lane l of a wave
@@ -368,10 +383,11 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                     for (int p0 = 0; p0 < rl; p0 += WAVE) {
                         if (p0 + lane < rl) {
                             const long long gi = src + p0 + lane;
-                            lds_dma(g.samples + gi, &L.st[0][rb + p0]);
-                            lds_dma(pv.u0 + gi, &L.st[1][rb + p0]);
-                            lds_dma(pv.u1 + gi, &L.st[2][rb + p0]);
-                            lds_dma(pv.u2sq + gi, &L.st[3][rb + p0]);
+                            const int at = Plane<W, CAP>::ZP + rb + p0;
+                            lds_dma(g.samples + gi, &L.st[0][at]);
+                            lds_dma(pv.u0 + gi, &L.st[1][at]);
+                            lds_dma(pv.u1 + gi, &L.st[2][at]);
+                            lds_dma(pv.u2sq + gi, &L.st[3][at]);
                         }
                     }
                 }
@@ -439,6 +455,7 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                                 const float u = 1.f - x;
                                 const int id = a + off;
                                 const float *sp = stage_at(&L.st[0][0], id);
+                                constexpr int PS = Plane<W, CAP>::STRIDE;
                                 float fw[W + 1];
 #pragma unroll
                                 for (int j = 0; j <= W; ++j) fw[j] = sp[j];
@@ -447,8 +464,8 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                                     U[p][j] = fmaf(u, fw[j], U[p][j]);
                                     U[p][j] = fmaf(x, fw[j + 1], U[p][j]);
                                 }
-                                const float tq = fmaf(x, sp[2 * CAP], sp[CAP]);
-                                D[p] += fmaf(tq, tq, sp[3 * CAP]);
+                                const float tq = fmaf(x, sp[2 * PS], sp[PS]);
+                                D[p] += fmaf(tq, tq, sp[3 * PS]);
                                 Mc[p] += 1.f;
                             }
                         } else {
@@ -466,14 +483,14 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                                 const double tau = fmin(sqrt_newton(T), 1073741824.0);
                                 const int a = (int)tau - HW;
                                 const bool ok = (unsigned)a <= (unsigned)lim;
-                                idx[p] = ok ? a + off : 0;
+                                idx[p] = ok ? a + off : 0;  // 0: the zero block
                                 xw[p] = ok ? (float)__builtin_amdgcn_fract(tau) : 0.f;
                                 vm[p] = ok ? 1.f : 0.f;
                                 uw[p] = vm[p] - xw[p];
                             }
-                            // a window that is off the trace reads a harmless in-range
-                            // LDS word with zero weights, so the loads of all P windows
-                            // can be in flight together
+                            // a window that is off the trace reads the zero block with
+                            // zero weights (adding exact zeros), so the loads of all P
+                            // windows can be in flight together
 #pragma unroll
                             for (int p = 0; p < P; ++p) {
                                 const int id = idx[p];
@@ -602,6 +619,29 @@ struct ShapeT<5, W> {
     static constexpr bool BRANCHY = true;
 };
 
+// Rows 64*sblk .. of a job whose aperture is longer than the caller declared:
+// best = -1, s_best = -1, stack = 0 and (if requested) panel cells of -1.
+__device__ __forceinline__ void write_apert_marker(const JobView &jv, int job, int sblk, int nsc, int npar,
+                                                   int32_t *best, float *s_best, float *stack, float *panel,
+                                                   __half *panel16)
+{
+    const int s0 = sblk * WAVE;
+    const int nr = min(WAVE, nsc - s0);
+    const int64_t row0 = jv.out_off[job] + s0;
+    if ((int)threadIdx.x < nr) {
+        best[row0 + threadIdx.x] = -1;
+        s_best[row0 + threadIdx.x] = -1.f;
+        stack[row0 + threadIdx.x] = 0.f;
+    }
+    if (panel || panel16) {
+        const int64_t ncell = (int64_t)nr * npar;
+        for (int64_t e = threadIdx.x; e < ncell; e += blockDim.x) {
+            if (panel) panel[row0 * npar + e] = -1.f;
+            if (panel16) panel16[row0 * npar + e] = __float2half(-1.f);
+        }
+    }
+}
+
 // The exhaustive scan: one workgroup per (job, sample block), all parameters.
 template <int KIND, int W, int SID>
 __global__ void __launch_bounds__((ShapeT<SID, W>::NW * WAVE))
@@ -614,7 +654,13 @@ scan_kernel(ScanArgs a)
     const int job = tile / a.j.n_sblk;
     const int sblk = tile - job * a.j.n_sblk;
     if (job >= a.j.njobs) return;
-    if (sblk * WAVE >= a.g.ns[a.j.central[job]]) return;  // uniform, before any barrier
+    const int nsc = a.g.ns[a.j.central[job]];
+    if (sblk * WAVE >= nsc) return;  // uniform, before any barrier
+    if (KIND == SEMB_KIND_CRS && apert_over(a.j.apert_ptr, a.j.max_apert, job)) {
+        write_apert_marker(a.j, job, sblk, nsc, a.p.npar, a.best, a.s_best, a.stack, a.panel,
+                           static_cast<__half *>(a.panel16));
+        return;
+    }
     float bS, bSt;
     int bI;
     scan_tile<KIND, W, S::P, S::NW, S::CAP, S::TMAX, S::BRANCHY>(a.g, a.j, a.p, L, job, sblk, 0, a.p.npar,

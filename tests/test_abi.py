@@ -274,6 +274,14 @@ def test_batch_plan_rejects_bad_input(semb):
     with pytest.raises(semb.SembError):
         semb.batch_plan(np.array([0], np.int32), np.array([3], np.int32), np.array([0, 1], np.int32),
                         np.array([0], np.int32), np.array([10], np.int32), np.array([0, 1], np.int32), 5, 5)
+    # a CRS aperture of more than SEMB_APERT_LIMIT (64) gathers cannot be scanned
+    ng = 70
+    ok = dict(ns=np.full(ng, 10, np.int32), trace_ptr=np.arange(ng + 1, dtype=np.int32))
+    semb.batch_plan(np.array([1], np.int32), np.array([30], np.int32), np.array([0, 64], np.int32),
+                    np.arange(64, dtype=np.int32), ok["ns"], ok["trace_ptr"], 5, 5)
+    with pytest.raises(semb.SembError, match="aperture"):
+        semb.batch_plan(np.array([1], np.int32), np.array([30], np.int32), np.array([0, 65], np.int32),
+                        np.arange(65, dtype=np.int32), ok["ns"], ok["trace_ptr"], 5, 5)
 
 
 def test_shape_names_and_host_side_table(semb):
