@@ -115,10 +115,11 @@ def test_off_trace_windows_over_a_short_stage_every_shape():
     rng = np.random.default_rng(41)
     ns, dt, w = 40, 0.004, 31
     q = synth.velocity_grid(1800, 2200, 9)
-    # tau(s = 0) = 26 samples at the middle velocity: beyond the last window
-    # start (ns - 1 - w = 8) for every s, and the union range of a tile's
-    # traces covers fewer than w + 1 samples at the end of the trace
-    h_far = np.float32(26 * dt / np.sqrt(4.0 / 2000.0 ** 2))
+    # tau(s = 0) = 25 samples at the fastest velocity (and more at the others):
+    # every window starts past the last valid start (ns - 1 - w = 8) for every
+    # s, and the union range a tile stages, samples 9..39, holds fewer than
+    # w + 1 = 32 samples
+    h_far = np.float32(25 * dt / np.sqrt(4.0 / 2200.0 ** 2))
     traces = [helpers.seismic_like(rng, 2, ns, dt).astype(np.float32),
               helpers.seismic_like(rng, 3, 200, dt).astype(np.float32)]
     hs = [np.array([h_far, h_far * 1.01], np.float32), np.array([0.0, 100.0, 250.0], np.float32)]
@@ -153,12 +154,13 @@ def test_aperture_longer_than_declared_gets_the_marker():
     import torch
     import paper_1907_11678_amd as semb
     wl = synth.crs_line(centrals=[10, 11], grid=synth.crs_coarse_grid())
-    gs = wl.gathers
+    gs = wl.gathers  # gathers renumbered: line gathers 6..15 are 0..9
+    c0, c1 = (int(c) for c in wl.jobs.central)
     # job 0: +-4 gathers (9), job 1: +-1 gather (3); declare at most 5
     ap = np.array([0, 9, 12], np.int32)
-    ag = np.array(list(range(6, 15)) + [10, 11, 12], np.int32)
-    ns = int(gs.ns[10])
-    jobs = synth.Jobs(central=np.array([10, 11], np.int32), apert_ptr=ap, apert_gather=ag,
+    ag = np.array(list(wl.jobs.apert_gather[:9]) + [c1 - 1, c1, c1 + 1], np.int32)
+    ns = int(gs.ns[c0])
+    jobs = synth.Jobs(central=np.array([c0, c1], np.int32), apert_ptr=ap, apert_gather=ag,
                       out_off=np.array([0, ns], np.int64), n_out=2 * ns)
     dg, dj = gu.device_inputs(gs, jobs)
     dj = dataclasses.replace(dj, max_apert=5)
