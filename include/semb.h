@@ -149,6 +149,23 @@ semb_status crs_scan(const semb_gathers *g, const semb_jobs *jobs, const float *
                      const float *B, int32_t nB, const float *q, int32_t nq, int32_t w,
                      const semb_outputs *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* The scan for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * cmp_scan (kind SEMB_KIND_CMP; A, B ignored) or crs_scan (SEMB_KIND_CRS)
+ * with the same arguments and the same outputs, bit for bit, but no
+ * workspace.  The window-energy planes go to a scratch array of
+ * SEMB_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * (until the process ends); the call allocates nothing and frees nothing.
+ * The gathers must fit it: semb_workspace_bytes(g->nsamples) <=
+ * SEMB_NOALLOC_SCRATCH_BYTES (about 5.5 million samples), else SEMB_EINVAL
+ * before anything is enqueued.  All calls on one GPU share its scratch, which
+ * keeps the last call's contents (nothing in it needs to start at zero):
+ * calls that overlap on one GPU (two streams, two threads) race. */
+#define SEMB_NOALLOC_SCRATCH_BYTES (64u << 20)
+semb_status semb_scan_noalloc(int32_t kind, const semb_gathers *g, const semb_jobs *jobs, const float *A,
+                              int32_t nA, const float *B, int32_t nB, const float *q, int32_t nq, int32_t w,
+                              const semb_outputs *out, hipStream_t stream);
+
 /* Semblance and stack of every output row at its own parameter theta[row] =
  * (A, B, q) (FP32 [n_out][3]; CMP ignores A and B).  s_out, stack_out:
  * [n_out], overwritten. */

@@ -91,6 +91,7 @@ def lib():
         L.semb_workspace_bytes.argtypes = [i64]
         L.semb_workspace_bytes.restype = C.c_size_t
         L.cmp_scan.argtypes = [P, P, P, i32, i32, P, P, C.c_size_t, P]
+        L.semb_scan_noalloc.argtypes = [i32, P, P, P, i32, P, i32, P, i32, i32, P, P]
         L.crs_scan.argtypes = [P, P, P, i32, P, i32, P, i32, i32, P, P, C.c_size_t, P]
         L.stack.argtypes = [P, P, i32, P, i32, P, P, P]
         L.semblance_grad.argtypes = [P, P, i32, P, P, i32, P, P, P]
@@ -351,6 +352,27 @@ def crs_scan(g: DeviceGathers, jobs: DeviceJobs, A, B, q, w: int, best, s_best, 
                           _typed(B, torch.float32, "B"), int(B.numel()),
                           _typed(q, torch.float32, "q"), int(q.numel()), int(w), C.byref(out),
                           _ptr(ws), int(ws.numel() * ws.element_size()), _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # SEMB_NOALLOC_SCRATCH_BYTES
+
+
+def scan_noalloc(kind: int, g: DeviceGathers, jobs: DeviceJobs, q, w: int, best, s_best, stack_out, A=None,
+                 B=None, panel=None, stream=None, panel_f16=None):
+    """The CMP (kind 0) or CRS (kind 1) scan without a workspace: the library's
+    per-GPU static scratch holds the window-energy planes (semb_scan_noalloc)."""
+    import torch
+    crs = int(kind) == 1
+    npar = (int(A.numel()) * int(B.numel()) if crs else 1) * int(q.numel())
+    _scan_outputs(jobs, npar, best, s_best, stack_out, panel, panel_f16)
+    gs, js, out = g.cstruct(), jobs.cstruct(), _outputs(best, s_best, stack_out, panel, panel_f16)
+    _check(lib().semb_scan_noalloc(int(kind), C.byref(gs), C.byref(js),
+                                   _typed(A, torch.float32, "A") if crs else None,
+                                   int(A.numel()) if crs else 1,
+                                   _typed(B, torch.float32, "B") if crs else None,
+                                   int(B.numel()) if crs else 1,
+                                   _typed(q, torch.float32, "q"), int(q.numel()), int(w), C.byref(out),
+                                   _stream(stream)))
 
 
 def stack(g: DeviceGathers, jobs: DeviceJobs, kind: int, theta, w: int, s_out, stack_out, stream=None):

@@ -207,10 +207,9 @@ const char *const kShapeNames[semb::kScanShapes] = {
     "16 waves x 4 parameters (2 for w > 15), 2048-sample stage, windows behind a branch",
 };
 
-// shape < 0: the tuned (or default) shape for this call's key
-semb_status scan_common(int kind, const semb_gathers *g, const semb_jobs *jobs, const float *A, int32_t nA,
-                        const float *B, int32_t nB, const float *q, int32_t nq, int32_t w,
-                        const semb_outputs *out, void *ws, size_t ws_bytes, hipStream_t stream, int shape = -1)
+// Every argument of a scan except the workspace (host fields only).
+semb_status check_scan(int kind, const semb_gathers *g, const semb_jobs *jobs, const float *A, int32_t nA,
+                       const float *B, int32_t nB, const float *q, int32_t nq, int32_t w, const semb_outputs *out)
 {
     const bool crs = kind == SEMB_KIND_CRS;
     TRY(check_gathers(g, crs));
@@ -225,6 +224,18 @@ semb_status scan_common(int kind, const semb_gathers *g, const semb_jobs *jobs, 
     if (jobs->njobs == 0) return SEMB_OK;  // nothing to compute, nothing is read or written
     if (!out || !out->best || !out->s_best || !out->stack)
         return fail(SEMB_EINVAL, "outputs best, s_best and stack are required");
+    return SEMB_OK;
+}
+
+// shape < 0: the tuned (or default) shape for this call's key
+semb_status scan_common(int kind, const semb_gathers *g, const semb_jobs *jobs, const float *A, int32_t nA,
+                        const float *B, int32_t nB, const float *q, int32_t nq, int32_t w,
+                        const semb_outputs *out, void *ws, size_t ws_bytes, hipStream_t stream, int shape = -1)
+{
+    const bool crs = kind == SEMB_KIND_CRS;
+    TRY(check_scan(kind, g, jobs, A, nA, B, nB, q, nq, w, out));
+    if (jobs->njobs == 0) return SEMB_OK;
+    const long long npar = crs ? (long long)nA * nB * nq : nq;
     const size_t need = semb_workspace_bytes(g->nsamples);
     if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign) != 0)
         return fail(SEMB_EWORKSPACE, "workspace must be %zu bytes, 256-byte aligned (got %zu at %p)", need,
@@ -321,6 +332,35 @@ BatchLayout batch_layout(int64_t nsamples, int32_t w_cmp, int32_t w_crs, int32_t
     L.partials = L.counters + round_up((size_t)(1 + (ngroups > 0 ? ngroups : 0)) * sizeof(unsigned));
     L.total = L.partials + round_up((size_t)(nparts > 0 ? nparts : 0) * 64 * sizeof(semb::Partial));
     return L;
+}
+
+// ---- the allocation-free scan's scratch --------------------------------------
+// The window-energy planes of semb_scan_noalloc live in this file-scope device
+// array (each GPU the library runs on holds its own copy until the process
+// ends).  In host code `scratch` names a host-side stand-in, not the device
+// copy: its device address is looked up once per device with
+// hipGetSymbolAddress and only that address is ever passed to a kernel.
+__device__ __align__(256) unsigned char scratch[SEMB_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_at;  // device ordinal -> address of its `scratch`
+
+semb_status scratch_address(void **at)
+{
+    int dev = 0;
+    TRY(hip_status(hipGetDevice(&dev), "semb_scan_noalloc: hipGetDevice"));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    const auto it = g_scratch_at.find(dev);
+    if (it != g_scratch_at.end()) {
+        *at = it->second;
+        return SEMB_OK;
+    }
+    void *p = nullptr;
+    TRY(hip_status(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "semb_scan_noalloc: hipGetSymbolAddress"));
+    if (!p) return fail(SEMB_EHIP, "semb_scan_noalloc: no device address for the scratch array");
+    g_scratch_at[dev] = p;
+    *at = p;
+    return SEMB_OK;
 }
 
 }  // namespace
@@ -519,6 +559,26 @@ semb_status crs_scan(const semb_gathers *g, const semb_jobs *jobs, const float *
                      size_t ws_bytes, hipStream_t stream)
 {
     return scan_common(SEMB_KIND_CRS, g, jobs, A, nA, B, nB, q, nq, w, out, ws, ws_bytes, stream);
+}
+
+semb_status semb_scan_noalloc(int32_t kind, const semb_gathers *g, const semb_jobs *jobs, const float *A, int32_t nA,
+                              const float *B, int32_t nB, const float *q, int32_t nq, int32_t w,
+                              const semb_outputs *out, hipStream_t stream)
+{
+    if (kind != SEMB_KIND_CMP && kind != SEMB_KIND_CRS) return fail(SEMB_EINVAL, "kind must be CMP or CRS");
+    if (!g || !jobs) return fail(SEMB_EINVAL, "gathers and jobs are required");
+    const size_t need = semb_workspace_bytes(g->nsamples);
+    if (need > (size_t)SEMB_NOALLOC_SCRATCH_BYTES)
+        return fail(SEMB_EINVAL,
+                    "semb_scan_noalloc: %lld samples need %zu bytes of window-energy scratch; the static "
+                    "scratch holds %zu (use cmp_scan / crs_scan with a workspace)",
+                    (long long)g->nsamples, need, (size_t)SEMB_NOALLOC_SCRATCH_BYTES);
+    TRY(check_scan(kind, g, jobs, A, nA, B, nB, q, nq, w, out));
+    if (jobs->njobs == 0) return SEMB_OK;
+    // the lookup below touches no device memory and allocates nothing
+    void *ws = nullptr;
+    TRY(scratch_address(&ws));
+    return scan_common(kind, g, jobs, A, nA, B, nB, q, nq, w, out, ws, (size_t)SEMB_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 semb_status stack(const semb_gathers *g, const semb_jobs *jobs, int32_t kind, const float *theta, int32_t w,

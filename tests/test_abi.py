@@ -121,6 +121,27 @@ def test_small_or_misaligned_workspace(semb):
     assert L.cmp_scan(C.byref(g), C.byref(j), P, 8, 11, C.byref(out), None, need, None) == 2
 
 
+def test_noalloc_scan_validates(semb):
+    """semb_scan_noalloc rejects gathers larger than its static scratch, and
+    every argument cmp_scan / crs_scan reject, before touching the device."""
+    L = semb.lib()
+    out = _outs(semb)
+    P = C.c_void_p(0x4000)
+    limit = semb.NOALLOC_SCRATCH_BYTES
+    assert semb.workspace_bytes(limit // 12 - 4096) <= limit < semb.workspace_bytes(limit // 12 + 4096)
+    g = _gathers(semb, nsamples=limit // 12 + 4096)
+    assert L.semb_scan_noalloc(0, C.byref(g), C.byref(_jobs(semb)), None, 1, None, 1, P, 8, 11, C.byref(out),
+                               None) == 1
+    assert "scratch" in semb.last_error()
+    g = _gathers(semb, nsamples=1000)
+    assert L.semb_scan_noalloc(0, C.byref(g), C.byref(_jobs(semb)), None, 1, None, 1, P, 8, 4, C.byref(out),
+                               None) == 1  # even w
+    assert L.semb_scan_noalloc(2, C.byref(g), C.byref(_jobs(semb)), None, 1, None, 1, P, 8, 11, C.byref(out),
+                               None) == 1  # bad kind
+    assert L.semb_scan_noalloc(1, C.byref(g), C.byref(_jobs(semb)), None, 1, None, 1, P, 8, 9, C.byref(out),
+                               None) == 1  # CRS without A, B
+
+
 def test_point_calls_validate(semb):
     L = semb.lib()
     g = _gathers(semb)
