@@ -61,12 +61,11 @@ __device__ __forceinline__ void lds_dma(const float *g, float *lds_base)
     __builtin_amdgcn_global_load_lds((void *)g, (lds_void *)lds_base, 4, 0, 0);
 }
 
-// Stage position id of a tile's LDS stage as one address that the optimiser
-// cannot re-derive, so the window's w + 1 samples and its three energy words
-// are all read from this address plus immediate offsets.
-__device__ __forceinline__ const float *stage_at(const float *stage, int id)
+// The LDS word `byte` bytes into a tile's stage, as one address that the
+// optimiser cannot re-derive, so the window's w + 1 samples and its three
+// energy words are all read from this address plus immediate offsets.
+__device__ __forceinline__ const float *stage_at(const float *stage, unsigned byte)
 {
-    unsigned byte = (unsigned)id * 4u;
     asm("" : "+v"(byte));
     return reinterpret_cast<const float *>(reinterpret_cast<const char *>(stage) + byte);
 }
@@ -127,8 +126,9 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk)
 // ---------------------------------------------------------------------------
 // What the hot loop needs of one trace, read with one LDS load (all 16 bytes
 // for CMP; CRS takes its traveltime terms from the parameter table and reads
-// the first 8): the last valid window start (-1: nothing staged), the LDS
-// position of the trace's sample 0 in its stage, and h^2/dt^2.
+// the first 8): the last valid window start (-1: nothing staged), the byte
+// offset in the stage such that the window of an intersection with floor k
+// starts at byte 4 k + off, and h^2/dt^2.
 struct __align__(16) TraceRun {
     int lim;
     int off;
@@ -292,13 +292,14 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
             }
         }
 
-        float U[P][W], D[P], Mc[P];
+        float U[P][W], D[P];
+        int Mi[P];  // contributing traces
 #pragma unroll
         for (int p = 0; p < P; ++p) {
 #pragma unroll
             for (int j = 0; j < W; ++j) U[p][j] = 0.f;
             D[p] = 0.f;
-            Mc[p] = 0.f;
+            Mi[p] = 0;
         }
 
         for (int tA = 0; tA < ntr; tA += TMAX) {
@@ -369,7 +370,8 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                     len = min(len, CAP);
                     incl = len;
                 }
-                if (wv == 0 && lane < nfit) L.run[e].off = Plane<W, CAP>::ZP + incl - len - L.t_lo[e];
+                // window start a = k - HW sits at stage position ZP + (incl - len) + a - lo
+                if (wv == 0 && lane < nfit) L.run[e].off = 4 * (Plane<W, CAP>::ZP + incl - len - L.t_lo[e] - HW);
 
                 // ---- stage the samples and their window energy -------------------
                 // Direct global->LDS loads (global_load_lds_dword): lane l of a wave
@@ -449,12 +451,11 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                                 // window start no trace has: the range test below
                                 // rejects those traces without a test on T
                                 const double tau = fmin(sqrt_newton(T), 1073741824.0);
-                                const int a = (int)tau - HW;
-                                if (!((unsigned)a <= (unsigned)lim)) continue;
+                                const int k = (int)tau;
+                                if (!((unsigned)(k - HW) <= (unsigned)lim)) continue;
                                 const float x = (float)__builtin_amdgcn_fract(tau);
                                 const float u = 1.f - x;
-                                const int id = a + off;
-                                const float *sp = stage_at(&L.st[0][0], id);
+                                const float *sp = stage_at(&L.st[0][0], ((unsigned)k << 2) + (unsigned)off);
                                 constexpr int PS = Plane<W, CAP>::STRIDE;
                                 float fw[W + 1];
 #pragma unroll
@@ -466,11 +467,15 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                                 }
                                 const float tq = fmaf(x, sp[2 * PS], sp[PS]);
                                 D[p] += fmaf(tq, tq, sp[3 * PS]);
-                                Mc[p] += 1.f;
+                                Mi[p] += 1;
                             }
                         } else {
-                            int idx[P];
-                            float xw[P], uw[P], vm[P];
+                            // every window is read: one that is off its trace reads
+                            // the zero block at byte 0 of each plane, and adds exact
+                            // zeros whatever its (finite) weights, so the loads of all
+                            // P windows can be in flight together
+                            unsigned addr[P];
+                            float xw[P], uw[P];
 #pragma unroll
                             for (int p = 0; p < P; ++p) {
                                 double T;
@@ -481,30 +486,27 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                                     T = fma(qd[p], cc, s2e);
                                 }
                                 const double tau = fmin(sqrt_newton(T), 1073741824.0);
-                                const int a = (int)tau - HW;
-                                const bool ok = (unsigned)a <= (unsigned)lim;
-                                idx[p] = ok ? a + off : 0;  // 0: the zero block
-                                xw[p] = ok ? (float)__builtin_amdgcn_fract(tau) : 0.f;
-                                vm[p] = ok ? 1.f : 0.f;
-                                uw[p] = vm[p] - xw[p];
+                                const int k = (int)tau;
+                                const bool ok = (unsigned)(k - HW) <= (unsigned)lim;
+                                addr[p] = ok ? ((unsigned)k << 2) + (unsigned)off : 0u;
+                                xw[p] = (float)__builtin_amdgcn_fract(tau);  // tau <= 2^30: finite
+                                uw[p] = 1.f - xw[p];
+                                Mi[p] += ok ? 1 : 0;
                             }
-                            // a window that is off the trace reads the zero block with
-                            // zero weights (adding exact zeros), so the loads of all P
-                            // windows can be in flight together
 #pragma unroll
                             for (int p = 0; p < P; ++p) {
-                                const int id = idx[p];
+                                const float *sp = stage_at(&L.st[0][0], addr[p]);
+                                constexpr int PS = Plane<W, CAP>::STRIDE;
                                 float fw[W + 1];
 #pragma unroll
-                                for (int j = 0; j <= W; ++j) fw[j] = L.st[0][id + j];
+                                for (int j = 0; j <= W; ++j) fw[j] = sp[j];
 #pragma unroll
                                 for (int j = 0; j < W; ++j) {
                                     U[p][j] = fmaf(uw[p], fw[j], U[p][j]);
                                     U[p][j] = fmaf(xw[p], fw[j + 1], U[p][j]);
                                 }
-                                const float tq = fmaf(xw[p], L.st[2][id], L.st[1][id]);
-                                D[p] = fmaf(vm[p], fmaf(tq, tq, L.st[3][id]), D[p]);
-                                Mc[p] += vm[p];
+                                const float tq = fmaf(xw[p], sp[2 * PS], sp[PS]);
+                                D[p] += fmaf(tq, tq, sp[3 * PS]);
                             }
                         }
                     }
@@ -527,8 +529,9 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                         N = fmaf(U[p][j], U[p][j], N);
                         Ls += U[p][j];
                     }
-                    const float S = (Mc[p] > 0.f && D[p] > 0.f) ? N / (Mc[p] * D[p]) : 0.f;
-                    const float st = (Mc[p] > 0.f) ? Ls / (Mc[p] * (float)W) : 0.f;
+                    const float Mc = (float)Mi[p];
+                    const float S = (Mc > 0.f && D[p] > 0.f) ? N / (Mc * D[p]) : 0.f;
+                    const float st = (Mc > 0.f) ? Ls / (Mc * (float)W) : 0.f;
                     if (panel) panel[row * pv.npar + th] = S;
                     if (panel16) panel16[row * pv.npar + th] = __float2half(S);
                     if (S > bS) {  // parameters visited in increasing index: first max wins
