@@ -532,9 +532,10 @@ int oracle_corrected(int kind, const float *samples, const int64_t *sample_off, 
  * Optional outputs for comparisons with an FP32 evaluation:
  *  - g_theta_mag [row][3], g_samples_mag (ACCUMULATED): the same sums with
  *    every term replaced by its magnitude and dS/dv_ij by its size before
- *    the subtraction cancels, 2 (sum_i |v_ij| + S M |v_ij|) / (M D).  An
- *    evaluation whose every term carries a relative error e differs by at
- *    most about e times these;
+ *    the subtraction cancels, 2 (sum_i |v_ij| + S M |v_ij|) / (M D); the
+ *    weight 1 - x of a window's first sample enters as 1, the size of the
+ *    rounding it inherits from x.  An evaluation whose every term carries a
+ *    relative error e differs by at most about e times these;
  *  - rough [row]: 1 if the row's cell is a kink (a contributing intersection
  *    within KINK_TAU samples of an integer) or fragile (its contributing set
  *    could change, as in oracle_scan);
@@ -650,8 +651,11 @@ int oracle_grad(int kind, const float *samples, const int64_t *sample_off, const
                             g_samples[base + a + jj + 1] += gs * x * dS_dv;
                         }
                         if (g_samples_mag) {
+                            /* the weight 1 - x, formed from an x rounded to FP32,
+                             * carries that rounding (of size x, not 1 - x): its
+                             * magnitude is (1 - x) + x = 1 */
 #pragma omp atomic
-                            g_samples_mag[base + a + jj] += fabs(gs) * (1.0 - x) * m_dv;
+                            g_samples_mag[base + a + jj] += fabs(gs) * m_dv;
 #pragma omp atomic
                             g_samples_mag[base + a + jj + 1] += fabs(gs) * x * m_dv;
                         }

@@ -135,3 +135,29 @@ def random_line(rng: np.random.Generator, ngathers: int, fold_range=(1, 4), ns_r
         hs.append(np.sort(rng.uniform(0, hmax, fold)).astype(np.float32))
         ms.append(np.full(fold, spacing * g, np.float32))
     return synth.pack_gathers(traces, hs, ms, [spacing * g for g in range(ngathers)], dt)
+
+
+def max_dtau_dtheta(gs, jobs, theta) -> np.ndarray:
+    """Per output row, the largest |d tau / d theta_k| (samples per unit of A,
+    B and q) over the row's aperture traces, from T = (t0 + 2 A dm)^2 +
+    2 t0 B dm^2 + q h^2 and tau = sqrt(T) / dt.  Only used to size
+    finite-difference steps so that no intersection moves further than a
+    chosen fraction of a sample."""
+    dt = float(gs.dt)
+    out = np.zeros((jobs.n_out, 3))
+    for j in range(jobs.njobs):
+        c = int(jobs.central[j])
+        idx = np.concatenate([np.arange(gs.trace_ptr[g], gs.trace_ptr[g + 1])
+                              for g in jobs.apert_gather[jobs.apert_ptr[j]:jobs.apert_ptr[j + 1]]])
+        dm = gs.midpoint[idx].astype(np.float64) - float(gs.central_x[c])
+        h = gs.half_offset[idx].astype(np.float64)
+        ns = int(gs.ns[c])
+        r0 = int(jobs.out_off[j])
+        t0 = (np.arange(ns) * dt)[:, None]
+        A, B, q = (np.asarray(theta, np.float64)[r0:r0 + ns, k][:, None] for k in range(3))
+        T = np.maximum((t0 + 2 * A * dm) ** 2 + 2 * t0 * B * dm * dm + q * h * h, 1e-30)
+        den = 2.0 * np.sqrt(T) * dt
+        out[r0:r0 + ns, 0] = (np.abs(4 * dm * (t0 + 2 * A * dm)) / den).max(1)
+        out[r0:r0 + ns, 1] = (np.abs(2 * t0 * dm * dm) / den).max(1)
+        out[r0:r0 + ns, 2] = (h * h / den).max(1)
+    return out

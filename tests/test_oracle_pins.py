@@ -303,25 +303,28 @@ def pin_gradient_fd(lib=None):
     g_s = np.random.default_rng(2).uniform(0.5, 1.5, ns)
     gt, gsm, det = oracle.grad("crs", gs, jobs, theta, g_s, w, library=lib, detail=True)
     S0, _, M, _ = oracle.point("crs", gs, jobs, theta, w, library=lib)
-    # the steps move every intersection by less than the oracle's default kink
-    # band of 1e-4 samples, so only rows it flags as rough can see a kink
-    steps = np.array([5e-5, 1e-8, 4e-8]) * 1e-4
+    # each row's step in each component moves every one of its intersections
+    # by at most 5e-5 samples, inside the oracle's default kink band of 1e-4:
+    # only rows it flags as rough can see a kink
+    rate = helpers.max_dtau_dtheta(gs, jobs, theta)
     rows = [r for r in range(40, ns - 20, 3) if M[r] > 0 and S0[r] > 0.05 and not det.rough[r]]
     if len(rows) < 60:
         bad.append(f"gradient FD: only {len(rows)} smooth rows to check")
     for k in range(3):
+        step = 5e-5 / np.maximum(rate[:, k], 1e-300)
         tp, tm = theta.copy(), theta.copy()
-        tp[:, k] += steps[k]
-        tm[:, k] -= steps[k]
+        tp[:, k] += step
+        tm[:, k] -= step
         sp, _, mp, _ = oracle.point("crs", gs, jobs, tp, w, library=lib)
         sm, _, mm, _ = oracle.point("crs", gs, jobs, tm, w, library=lib)
-        fd = g_s * (sp - sm) / (2 * steps[k])
+        fd = g_s * (sp - sm) / (2 * step)
         nerr = 0
         for r in rows:
             if mp[r] != M[r] or mm[r] != M[r]:
                 continue
             scale = abs(fd[r]) + abs(gt[r, k]) + 1e-30
-            if abs(fd[r] - gt[r, k]) > 1e-4 * scale + 1e-9 * abs(g_s[r] / steps[k]) * 1e-6:
+            # FP64 rounding of S (~1e-15) divided by the step bounds the rest
+            if abs(fd[r] - gt[r, k]) > 1e-4 * scale + 1e-12 * abs(g_s[r]) / step[r]:
                 nerr += 1
         if nerr:
             bad.append(f"gradient FD component {k}: {nerr} of {len(rows)} rows disagree")
