@@ -250,10 +250,14 @@ point_kernel(PointArgs a)
 
 // Gradient-ascent refinement of every output sample's parameter, all steps in
 // one kernel (rows are independent).  In coordinates normalised by the grid
-// spacing (u = theta / scale) each step moves u a distance eta along the
-// ascent direction dS/du / |dS/du| (theta += eta * scale^2 * g / |scale * g|),
-// clamped to [lo, hi]; a step is kept only if S increases (then eta grows by
-// 1.25), otherwise eta halves.  Writes the refined theta, its S and stack.
+// spacing (u = theta / scale) every component takes its own step: it moves
+// u_k by eta_k in the direction of the sign of dS/du_k, clamped to [lo, hi];
+// eta_k grows by `grow` while the sign of its derivative repeats from the
+// last accepted step and halves when it flips.  A step is kept only if S
+// increases; otherwise every eta_k halves and the sign memory is cleared.
+// (Per-component step lengths follow the anisotropy of S in (A, B, q), and
+// sign steps are not thrown off by the jumps of the gradient where an
+// intersection crosses a sample.)  Writes the refined theta, its S and stack.
 template <int KIND, int W>
 __global__ void __launch_bounds__(WAVE)
 refine_kernel(PointArgs a, RefineArgs o)
@@ -271,32 +275,40 @@ refine_kernel(PointArgs a, RefineArgs o)
     if (KIND == SEMB_KIND_CMP) th[0] = th[1] = 0.f;
     Sums<W> cur = sums_at<KIND, W>(a, r, s, th[0], th[1], th[2]);
     float S = cur.S();
-    float eta = o.eta0;
+    float eta[3] = {o.eta0, o.eta0, o.eta0};
+    float last[3] = {0.f, 0.f, 0.f};  // signs of the last accepted step (0: none)
+    constexpr int K0 = KIND == SEMB_KIND_CMP ? 2 : 0;  // CMP moves q only
     for (int it = 0; it < o.steps; ++it) {
         float g[3];
         grad_at<KIND, W>(a, r, s, th[0], th[1], th[2], cur, 1.f, nullptr, g[0], g[1], g[2]);
-        float gu[3], nrm = 0.f;
+        float tr[3] = {th[0], th[1], th[2]};
+        float sg[3] = {0.f, 0.f, 0.f};
+        bool any = false;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            gu[k] = o.scale[k] * g[k];  // dS/du
-            nrm = fmaf(gu[k], gu[k], nrm);
+        for (int k = K0; k < 3; ++k) {
+            sg[k] = g[k] > 0.f ? 1.f : (g[k] < 0.f ? -1.f : 0.f);
+            const float same = sg[k] * last[k];
+            eta[k] *= same > 0.f ? o.grow : (same < 0.f ? 0.5f : 1.f);
+            tr[k] = fminf(fmaxf(fmaf(sg[k] * eta[k], o.scale[k], th[k]), o.lo[k]), o.hi[k]);
+            any |= sg[k] != 0.f;
         }
-        if (!(nrm > 0.f)) break;  // flat (or S = 0): nothing to climb
-        const float inv = eta * rsqrtf(nrm);
-        float tr[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) tr[k] = fminf(fmaxf(fmaf(o.scale[k] * inv, gu[k], th[k]), o.lo[k]), o.hi[k]);
-        if (KIND == SEMB_KIND_CMP) tr[0] = tr[1] = 0.f;
+        if (!any) break;  // flat (or S = 0): nothing to climb
         const Sums<W> nxt = sums_at<KIND, W>(a, r, s, tr[0], tr[1], tr[2]);
         const float Sn = nxt.S();
         if (Sn > S) {
             S = Sn;
             cur = nxt;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) th[k] = tr[k];
-            eta *= o.grow;
+            for (int k = 0; k < 3; ++k) {
+                th[k] = tr[k];
+                last[k] = sg[k];
+            }
         } else {
-            eta *= 0.5f;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                eta[k] *= 0.5f;
+                last[k] = 0.f;
+            }
         }
     }
 #pragma unroll

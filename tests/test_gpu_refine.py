@@ -107,20 +107,45 @@ def test_refinement_is_monotone_and_reports_its_semblance():
 
 
 def test_refinement_reaches_the_fine_grid():
-    """Coarse 7x7x11 + 8 ascent steps against the exhaustive 21x21x41 scan."""
+    """Coarse 7x7x11 scan, its 4 best local maxima per row as starts, 32 sign
+    steps from each (the bench's rule), against the exhaustive 21x21x41 scan.
+    The refined S reaches the fine grid's (within 1e-4) on at least 85% of
+    the rows (S_fine > 0.1) and the 5th percentile of the gap is above -0.02.
+    The rows short by more than 0.01 are reported with how many have no start
+    within one coarse cell of the fine grid's optimum (a basin the coarse
+    grid's peaks miss)."""
     import torch
+    import paper_1907_11678_amd as semb
     wl = synth.crs_line(centrals=[120, 121])
-    r = Refinement(wl)
-    r.run()
+    r = Refinement(wl, steps=32)
+    n, K, coarse = r.n, 4, r.coarse
+    panel = torch.empty((n, coarse.n), device="cuda")
+    semb.crs_scan(r.dg, r.dj, r.A, r.B, r.q, wl.w, r.best, r.s0, r.st0, r.ws, panel=panel)
+    theta_k = torch.empty((K, n, 3), device="cuda")
+    s_k = torch.empty((K, n), device="cuda")
+    st_k = torch.empty((K, n), device="cuda")
+    best_k = torch.empty((K, n), dtype=torch.int32, device="cuda")
+    peak_s = torch.empty((K, n), device="cuda")
+    S = torch.empty(n, device="cuda")
+    st = torch.empty(n, device="cuda")
+    th = torch.empty((n, 3), device="cuda")
+    semb.refine_multistart(r.dg, r.dj, 1, panel, r.A, r.B, r.q, wl.w, K, theta_k, s_k, st_k, best_k, peak_s, S, st,
+                           th, steps=r.steps, eta0=0.5, scale=r.scale, lo=r.lo, hi=r.hi)
     fine = gu.run_scan("crs", wl.gathers, wl.jobs, wl.grid, wl.w, dg=r.dg, dj=r.dj)
     torch.cuda.synchronize()
-    S = r.S.cpu().numpy().astype(np.float64)
+    Sr = S.cpu().numpy().astype(np.float64)
     Sf = fine[1]
     sel = Sf > 0.1
-    d = (S - Sf)[sel]
+    d = (Sr - Sf)[sel]
+    thf = oracle.theta_of(wl.grid, fine[0], "crs")
+    starts = np.stack([oracle.theta_of(coarse, b, "crs") for b in best_k.cpu().numpy()])
+    dist = (np.abs(starts - thf[None]) / np.asarray(r.scale)).max(axis=2).min(axis=0)
+    short = sel & (Sr < Sf - 0.01)
     _say(f"refined - fine-grid S over {sel.sum()} rows: median {np.median(d):+.4f}, "
-         f"p5 {np.percentile(d, 5):+.4f}, >= -1e-4: {(d >= -1e-4).mean():.3f}")
-    assert np.median(d) > -0.02
+         f"p5 {np.percentile(d, 5):+.4f}, >= -1e-4: {(d >= -1e-4).mean():.3f}; short by > 0.01: "
+         f"{int(short.sum())}, of them with no start within one coarse cell: {int((short & (dist > 1)).sum())}")
+    assert (d >= -1e-4).mean() >= 0.85
+    assert np.percentile(d, 5) > -0.02
 
 
 def test_refinement_graph_replay():
