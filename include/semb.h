@@ -190,8 +190,10 @@ semb_status semblance_grad(const semb_gathers *g, const semb_jobs *jobs, int32_t
  * ------------------------------------------------------------------------- */
 typedef struct semb_refine_opts {
     int32_t steps;    /* ascent steps, >= 0                                        */
-    float eta0;       /* initial step length in normalised units (grid cells), >= 0 */
-    float grow;       /* step growth after an accepted step, >= 1 (e.g. 1.25)       */
+    float eta0;       /* initial step length of every component in normalised
+                         units (grid cells), >= 0                                  */
+    float grow;       /* growth of a component's step while the sign of its
+                         derivative repeats, >= 1 (e.g. 1.2)                       */
     float scale[3];   /* unit of the normalised coordinates per component (A, B, q),
                          e.g. the coarse grid spacing                              */
     float lo[3];      /* the parameters stay inside [lo, hi] per component         */
@@ -200,12 +202,14 @@ typedef struct semb_refine_opts {
 
 /* Gradient-ascent refinement of each output row's parameter theta[row] =
  * (A, B, q) (FP32 [n_out][3], read and overwritten; CMP keeps A = B = 0).  In
- * coordinates u = theta / scale each step moves u a distance eta along the
- * ascent direction dS/du / |dS/du| (dS/dtheta as in semblance_grad), clamps
- * to [lo, hi], and keeps the step only if S increases (eta then grows by the
- * factor `grow`); otherwise eta halves.  Writes the final S and stack to s_out,
- * stack_out [n_out].  Rows are independent; the whole loop runs on the device
- * in one launch. */
+ * coordinates u = theta / scale every component k takes its own step: u_k
+ * moves eta_k in the direction of the sign of dS/du_k (dS/dtheta as in
+ * semblance_grad), clamped to [lo, hi].  eta_k starts at eta0, grows by the
+ * factor `grow` while the sign of its derivative repeats from the last
+ * accepted step and halves when it flips.  A step is kept only if S
+ * increases; otherwise every eta_k halves and the sign memory is cleared.
+ * Writes the final S and stack to s_out, stack_out [n_out].  Rows are
+ * independent; the whole loop runs on the device in one launch. */
 semb_status semb_refine(const semb_gathers *g, const semb_jobs *jobs, int32_t kind, float *theta,
                         const semb_refine_opts *o, int32_t w, float *s_out, float *stack_out,
                         hipStream_t stream);
@@ -313,6 +317,44 @@ typedef struct semb_batch {
 size_t semb_batch_workspace_bytes(int64_t nsamples, int32_t w_cmp, int32_t w_crs, int32_t ngroups,
                                   int32_t nparts);
 
+/* Tile shapes of the batched scan: the CRS tile of the persistent kernel comes
+ * in SEMB_BATCH_SHAPES shapes (windows behind a branch or branch-free, LDS
+ * stage of 2048 or 2560 samples; CMP tiles are the same in every shape, and
+ * every shape gives bit-identical outputs).  scan_batch uses the shape
+ * recorded for its key (w_cmp, w_crs and the traces-per-job and
+ * samples-per-trace buckets of semb_tune_scan), shape 0 without an entry.
+ * The entry also holds the split_params the recorded plan was built with
+ * (semb_batch_choice returns it, 256 without an entry), so that a caller can
+ * plan with the tuned split.  The paper tunes its tile to the local store
+ * (section 3.3.2); these are the batch kernel's counterpart. */
+#define SEMB_BATCH_SHAPES 3
+
+/* Human-readable description of a batch shape, NULL if out of range. [host] */
+const char *semb_batch_shape_name(int32_t shape);
+
+/* Record (shape, split_params) for the key of (w_cmp, w_crs, g, jobs); shape -1
+ * removes the entry.  Reads only host fields. [host] */
+semb_status semb_set_batch_choice(int32_t w_cmp, int32_t w_crs, const semb_gathers *g, const semb_jobs *jobs,
+                                  int32_t shape, int32_t split_params);
+
+/* The batch shape and split_params recorded for this key (defaults 0 and 256);
+ * either output may be NULL. [host] */
+void semb_batch_choice(int32_t w_cmp, int32_t w_crs, const semb_gathers *g, const semb_jobs *jobs, int32_t *shape,
+                       int32_t *split_params);
+
+/* Times every batch shape on a planned batch (arguments as for scan_batch; the
+ * plan built with split_params), one warm-up and `reps` timed launches each,
+ * compares each shape's best / s_best / stack over all n_out rows with shape
+ * 0's, and records the fastest shape whose outputs are bit-identical,
+ * together with split_params, for this key (another shape must beat shape 0
+ * by 2%).  *shape receives it, ms[SEMB_BATCH_SHAPES] (nullable, host) each
+ * shape's mean time in milliseconds, or -1 for a shape whose outputs differed.
+ * The outputs are overwritten.  Synchronizes `stream`: not for graph capture. */
+semb_status semb_tune_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_batch *b, const semb_tile *tiles,
+                            int64_t ntiles, int32_t ngroups, int32_t nparts, int32_t split_params, int32_t reps,
+                            const semb_outputs *out, void *ws, size_t ws_bytes, int32_t *shape, float *ms,
+                            hipStream_t stream);
+
 /* Run a planned batch (tiles: device copy of the plan).  Outputs as for the
  * scans (panel must be NULL); best indexes the job's own grid.  The workspace
  * holds the window-energy planes, the tile and group counters (reset by a
@@ -366,8 +408,19 @@ semb_status semb_set_scan_shape(int32_t kind, int32_t w, const semb_gathers *g, 
 /* The shape a scan with these arguments uses (-1 for invalid arguments). [host] */
 int32_t semb_scan_shape(int32_t kind, int32_t w, const semb_gathers *g, const semb_jobs *jobs);
 
-/* Forget every recorded shape. [host] */
+/* Forget every recorded shape (exhaustive scans and batches). [host] */
 void semb_clear_tuning(void);
+
+/* The tuning table on disk, so that tuned choices outlive the process.  Text,
+ * one entry per line: "scan <kind> <w> <traces bucket> <ns bucket> <shape>"
+ * and "batch <w_cmp> <w_crs> <traces bucket> <ns bucket> <shape>
+ * <split_params>" ('#' lines are comments).  semb_tuning_save writes every
+ * recorded entry; semb_tuning_load merges a file's entries into the table
+ * (an entry replaces the one with its key) only if every line is valid.
+ * Both return the number of entries, or -1 (semb_last_error) if the file
+ * cannot be opened or holds a line that is not an entry. [host] */
+int32_t semb_tuning_save(const char *path);
+int32_t semb_tuning_load(const char *path);
 
 /* CRS apertures by radius: for every central gather, the gathers whose
  * midpoint (x, y) lies within `radius` of the central's (the paper's

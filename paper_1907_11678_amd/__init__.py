@@ -123,6 +123,18 @@ def lib():
         L.semb_panel_peaks.restype = C.c_int
         L.semb_best_of.argtypes = [i32, i64, P, P, P, P, P, P, P]
         L.semb_best_of.restype = C.c_int
+        L.semb_batch_shape_name.argtypes = [i32]
+        L.semb_batch_shape_name.restype = C.c_char_p
+        L.semb_set_batch_choice.argtypes = [i32, i32, P, P, i32, i32]
+        L.semb_set_batch_choice.restype = C.c_int
+        L.semb_batch_choice.argtypes = [i32, i32, P, P, P, P]
+        L.semb_batch_choice.restype = None
+        L.semb_tune_batch.argtypes = [P, P, P, P, i64, i32, i32, i32, i32, P, P, C.c_size_t, P, P, P]
+        L.semb_tune_batch.restype = C.c_int
+        L.semb_tuning_save.argtypes = [C.c_char_p]
+        L.semb_tuning_save.restype = C.c_int32
+        L.semb_tuning_load.argtypes = [C.c_char_p]
+        L.semb_tuning_load.restype = C.c_int32
         L.semb_radius_apertures.argtypes = [P, P, i32, P, i32, C.c_double, P, P, P]
         L.semb_radius_apertures.restype = i64
         L.semb_kernel_timer_start.argtypes = [i32]
@@ -486,6 +498,23 @@ def clear_tuning():
     lib().semb_clear_tuning()
 
 
+def save_tuning(path: str) -> int:
+    """Write the tuning table (scan and batch choices) to `path`; returns the
+    number of entries."""
+    n = int(lib().semb_tuning_save(os.fsencode(path)))
+    if n < 0:
+        raise SembError(1, last_error())
+    return n
+
+
+def load_tuning(path: str) -> int:
+    """Merge the entries of a saved tuning table into the process's table."""
+    n = int(lib().semb_tuning_load(os.fsencode(path)))
+    if n < 0:
+        raise SembError(1, last_error())
+    return n
+
+
 # ---------------------------------------------------------------------------
 # batched scan (mixed CMP / CRS jobs, one persistent launch)
 # ---------------------------------------------------------------------------
@@ -507,6 +536,77 @@ def batch_plan(kind, central, apert_ptr, apert_gather, ns, trace_ptr, npar_cmp: 
     if n2 != n:
         raise SembError(1, last_error())
     return tiles[:n], int(ng.value), int(npart.value)
+
+
+BATCH_SHAPES = 3  # SEMB_BATCH_SHAPES
+
+
+def batch_shape_name(shape: int) -> str | None:
+    r = lib().semb_batch_shape_name(int(shape))
+    return r.decode() if r else None
+
+
+def set_batch_choice(w_cmp: int, w_crs: int, g: DeviceGathers, jobs: DeviceJobs, shape: int, split_params: int = 256):
+    gs, js = g.cstruct(), jobs.cstruct()
+    _check(lib().semb_set_batch_choice(int(w_cmp), int(w_crs), C.byref(gs), C.byref(js), int(shape),
+                                       int(split_params)))
+
+
+def batch_choice(w_cmp: int, w_crs: int, g: DeviceGathers, jobs: DeviceJobs) -> tuple[int, int]:
+    """(batch shape, split_params) recorded for this key (defaults 0, 256)."""
+    gs, js = g.cstruct(), jobs.cstruct()
+    sh, sp = C.c_int32(0), C.c_int32(0)
+    lib().semb_batch_choice(int(w_cmp), int(w_crs), C.byref(gs), C.byref(js), C.byref(sh), C.byref(sp))
+    return int(sh.value), int(sp.value)
+
+
+def tune_batch(g: DeviceGathers, jobs: DeviceJobs, kind_host, kind, q_cmp, w_cmp: int, A, B, q_crs, w_crs: int,
+               central, apert_ptr, apert_gather, ns, trace_ptr, best, s_best, stack_out, splits=(256, 1024),
+               reps: int = 1, sample_jobs: int | None = None, stream=None):
+    """Choose the batch tile shape and parameter split: for each split, plan the
+    first `sample_jobs` jobs (all by default; host arrays), time every shape
+    with semb_tune_batch (shapes whose outputs differ from shape 0's are
+    excluded), and require the outputs of every split to equal the first
+    split's bit for bit; record the fastest (shape, split) for the key of the
+    whole batch (g, jobs) and return (shape, split, {split: [ms per shape]}).
+    Synchronizes the stream."""
+    import torch
+    nj = len(central) if sample_jobs is None else min(int(sample_jobs), len(central))
+    kind_host, central = np.asarray(kind_host)[:nj], np.asarray(central)[:nj]
+    apert_ptr = np.asarray(apert_ptr)[:nj + 1]
+    nA, nB = int(A.numel()), int(B.numel())
+    gs, js = g.cstruct(), jobs.cstruct()
+    b = CBatch(_typed(kind, torch.int32, "kind"), _typed(q_cmp, torch.float32, "q_cmp"), int(q_cmp.numel()),
+               int(w_cmp), _typed(A, torch.float32, "A"), nA, _typed(B, torch.float32, "B"), nB,
+               _typed(q_crs, torch.float32, "q_crs"), int(q_crs.numel()), int(w_crs))
+    out = _outputs(best, s_best, stack_out, None)
+    times, ref, choice = {}, None, None
+    for split in splits:
+        tiles, ng, npart = batch_plan(kind_host, central, apert_ptr, apert_gather, ns, trace_ptr,
+                                      int(q_cmp.numel()), nA * nB * int(q_crs.numel()), split)
+        dt = torch.from_numpy(tiles).to(best.device)
+        ws = alloc_batch_workspace(g.nsamples, w_cmp, w_crs, ng, npart, device=best.device)
+        shape = C.c_int32(-1)
+        ms = (C.c_float * BATCH_SHAPES)()
+        _check(lib().semb_tune_batch(C.byref(gs), C.byref(js), C.byref(b), _typed(dt, torch.int32, "tiles"),
+                                     int(tiles.shape[0]), ng, npart, int(split), int(reps), C.byref(out), _ptr(ws),
+                                     int(ws.numel() * ws.element_size()), C.byref(shape), ms, _stream(stream)))
+        # the outputs of the shape just recorded (the last shape timed may have been excluded)
+        scan_batch(g, jobs, kind, q_cmp, w_cmp, A, B, q_crs, w_crs, dt, ng, npart, best, s_best, stack_out, ws,
+                   stream=stream)
+        torch.cuda.synchronize()
+        # bit patterns, so that rows no sampled job writes (whatever they hold, NaN included) compare equal
+        got = tuple(t.view(torch.int32).clone() for t in (best, s_best, stack_out))
+        if ref is None:
+            ref = got
+        elif not all(torch.equal(x, y) for x, y in zip(got, ref)):
+            continue  # a split whose outputs differ is never chosen
+        times[split] = [float(x) for x in ms]
+        t = times[split][int(shape.value)]
+        if choice is None or t < choice[2]:
+            choice = (int(shape.value), int(split), t)
+    set_batch_choice(w_cmp, w_crs, g, jobs, choice[0], choice[1])
+    return choice[0], choice[1], times
 
 
 def batch_workspace_bytes(nsamples: int, w_cmp: int, w_crs: int, ngroups: int, nparts: int) -> int:
@@ -556,7 +656,7 @@ def theta_from_best(best, q, theta, A=None, B=None, stream=None):
 
 def refine(g: DeviceGathers, jobs: DeviceJobs, kind: int, theta, w: int, s_out, stack_out, steps: int = 8,
            eta0: float = 0.5, scale=(1.0, 1.0, 1.0), lo=(-1e30, -1e30, -1e30), hi=(1e30, 1e30, 1e30),
-           stream=None, grow: float = 1.25):
+           stream=None, grow: float = 1.2):
     """Gradient-ascent refinement of theta [n_out, 3] in place (see semb_refine)."""
     import torch
     n = jobs.n_out if jobs.njobs > 0 else 0
@@ -636,7 +736,7 @@ def best_of(s_k, stack_k, theta_k, s_out, stack_out, theta_out, stream=None):
 def refine_multistart(g: DeviceGathers, jobs: DeviceJobs, kind: int, panel, A, B, q, w: int, K: int, theta_k,
                       s_k, stack_k, best_k, peak_s, s_out, stack_out, theta_out, steps: int = 8,
                       eta0: float = 0.5, scale=(1.0, 1.0, 1.0), lo=(-1e30, -1e30, -1e30), hi=(1e30, 1e30, 1e30),
-                      grow: float = 1.25, stream=None):
+                      grow: float = 1.2, stream=None):
     """Refinement from the K best local maxima of a coarse scan's panel: peaks,
     K ascents, best of K.  Scratch tensors: theta_k [K, n, 3], s_k, stack_k
     [K, n] (FP32), best_k [K, n] (int32), peak_s [K, n] (FP32)."""

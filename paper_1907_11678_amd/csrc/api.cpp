@@ -191,6 +191,32 @@ ShapeKey shape_key(int kind, int w, const semb_gathers *g, const semb_jobs *jobs
 
 int default_shape(int kind) { return kind == SEMB_KIND_CRS ? 2 : 0; }
 
+// The batched scan's choices: tile shape and parameter split per (w_cmp, w_crs,
+// traces per job, samples per trace), the sizes as in ShapeKey.
+struct BatchKey {
+    int wc, wr, traces, ns;
+    bool operator<(const BatchKey &o) const { return std::tie(wc, wr, traces, ns) < std::tie(o.wc, o.wr, o.traces, o.ns); }
+};
+struct BatchChoice {
+    int shape, split;
+};
+constexpr int kDefaultBatchShape = 0;
+constexpr int kDefaultBatchSplit = 256;
+std::map<BatchKey, BatchChoice> g_batch;  // guarded by g_shape_mu
+
+BatchKey batch_key(int wc, int wr, const semb_gathers *g, const semb_jobs *jobs)
+{
+    const ShapeKey k = shape_key(SEMB_KIND_CRS, wr, g, jobs);
+    return BatchKey{wc, wr, k.traces, k.ns};
+}
+
+BatchChoice chosen_batch(int wc, int wr, const semb_gathers *g, const semb_jobs *jobs)
+{
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    const auto it = g_batch.find(batch_key(wc, wr, g, jobs));
+    return it == g_batch.end() ? BatchChoice{kDefaultBatchShape, kDefaultBatchSplit} : it->second;
+}
+
 int chosen_shape(int kind, int w, const semb_gathers *g, const semb_jobs *jobs)
 {
     std::lock_guard<std::mutex> lk(g_shape_mu);
@@ -469,9 +495,27 @@ size_t semb_batch_workspace_bytes(int64_t nsamples, int32_t w_cmp, int32_t w_crs
     return batch_layout(nsamples, w_cmp, w_crs, ngroups, nparts).total;
 }
 
-semb_status scan_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_batch *b, const semb_tile *tiles,
-                       int64_t ntiles, int32_t ngroups, int32_t nparts, const semb_outputs *out, void *ws,
-                       size_t ws_bytes, hipStream_t stream)
+}  // extern "C"
+
+namespace {
+semb_status batch_common(const semb_gathers *g, const semb_jobs *jobs, const semb_batch *b, const semb_tile *tiles,
+                         int64_t ntiles, int32_t ngroups, int32_t nparts, const semb_outputs *out, void *ws,
+                         size_t ws_bytes, hipStream_t stream, int shape);
+}  // namespace
+
+extern "C" semb_status scan_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_batch *b,
+                                  const semb_tile *tiles, int64_t ntiles, int32_t ngroups, int32_t nparts,
+                                  const semb_outputs *out, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    return batch_common(g, jobs, b, tiles, ntiles, ngroups, nparts, out, ws, ws_bytes, stream, -1);
+}
+
+namespace {
+
+// shape < 0: the tuned (or default) batch shape for this call's key
+semb_status batch_common(const semb_gathers *g, const semb_jobs *jobs, const semb_batch *b, const semb_tile *tiles,
+                         int64_t ntiles, int32_t ngroups, int32_t nparts, const semb_outputs *out, void *ws,
+                         size_t ws_bytes, hipStream_t stream, int shape)
 {
     TRY(check_gathers(g, true));
     TRY(check_jobs(jobs, true, g));
@@ -538,8 +582,13 @@ semb_status scan_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_
     a.best = out->best;
     a.s_best = out->s_best;
     a.stack = out->stack;
-    return hip_status(timed(stream, [&] { return semb::launch_batch(a, ngroups, stream); }), "scan_batch launch");
+    const int bs = shape >= 0 ? shape : chosen_batch(b->w_cmp, b->w_crs, g, jobs).shape;
+    return hip_status(timed(stream, [&] { return semb::launch_batch(a, ngroups, bs, stream); }), "scan_batch launch");
 }
+
+}  // namespace
+
+extern "C" {
 
 
 size_t semb_workspace_bytes(int64_t nsamples)
@@ -777,6 +826,7 @@ void semb_clear_tuning(void)
 {
     std::lock_guard<std::mutex> lk(g_shape_mu);
     g_shapes.clear();
+    g_batch.clear();
 }
 
 semb_status semb_tune_scan(const semb_gathers *g, const semb_jobs *jobs, int32_t kind, const float *A, int32_t nA,
@@ -923,6 +973,188 @@ semb_status semb_tune_scan(const semb_gathers *g, const semb_jobs *jobs, int32_t
     }
     *shape = best_shape;
     return SEMB_OK;
+}
+
+const char *semb_batch_shape_name(int32_t shape)
+{
+    static const char *const names[semb::kBatchShapes] = {
+        "CRS tiles 8 waves x 4 parameters (2 for w > 9), windows behind a branch, 2048-sample stage",
+        "CRS tiles 8 waves x 4 parameters (2 for w > 9), branch-free windows, 2560-sample stage",
+        "CRS tiles 8 waves x 4 parameters (2 for w > 9), branch-free windows, 2048-sample stage",
+    };
+    return (shape >= 0 && shape < semb::kBatchShapes) ? names[shape] : nullptr;
+}
+
+semb_status semb_set_batch_choice(int32_t w_cmp, int32_t w_crs, const semb_gathers *g, const semb_jobs *jobs,
+                                  int32_t shape, int32_t split_params)
+{
+    if (!g || !jobs) return fail(SEMB_EINVAL, "semb_set_batch_choice: g and jobs are required");
+    if (shape < -1 || shape >= semb::kBatchShapes || (shape >= 0 && split_params < 1))
+        return fail(SEMB_EINVAL, "semb_set_batch_choice: shape must be -1 .. %d and split_params >= 1",
+                    semb::kBatchShapes - 1);
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    const BatchKey key = batch_key(w_cmp, w_crs, g, jobs);
+    if (shape < 0)
+        g_batch.erase(key);
+    else
+        g_batch[key] = BatchChoice{shape, split_params};
+    return SEMB_OK;
+}
+
+void semb_batch_choice(int32_t w_cmp, int32_t w_crs, const semb_gathers *g, const semb_jobs *jobs, int32_t *shape,
+                       int32_t *split_params)
+{
+    BatchChoice c{kDefaultBatchShape, kDefaultBatchSplit};
+    if (g && jobs) c = chosen_batch(w_cmp, w_crs, g, jobs);
+    if (shape) *shape = c.shape;
+    if (split_params) *split_params = c.split;
+}
+
+semb_status semb_tune_batch(const semb_gathers *g, const semb_jobs *jobs, const semb_batch *b, const semb_tile *tiles,
+                            int64_t ntiles, int32_t ngroups, int32_t nparts, int32_t split_params, int32_t reps,
+                            const semb_outputs *out, void *ws, size_t ws_bytes, int32_t *shape, float *ms,
+                            hipStream_t stream)
+{
+    if (!shape || reps < 1 || split_params < 1)
+        return fail(SEMB_EINVAL, "semb_tune_batch: shape must be non-NULL, reps and split_params >= 1");
+    // a first call validates every argument the same way scan_batch does
+    TRY(batch_common(g, jobs, b, tiles, ntiles, ngroups, nparts, out, ws, ws_bytes, stream, kDefaultBatchShape));
+    for (int k = 0; k < semb::kBatchShapes && ms; ++k) ms[k] = -1.f;
+    const size_t n = (size_t)std::max<int64_t>(jobs->n_out, 0);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TRY(hip_status(hipEventCreate(&e0), "hipEventCreate"));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SEMB_EHIP, "hipEventCreate failed");
+    }
+    std::vector<int32_t> rb(n), cb(n);
+    std::vector<float> rs(n), rt(n), cs(n), ct(n);
+    auto fetch = [&](std::vector<int32_t> &bb, std::vector<float> &ss, std::vector<float> &tt) -> semb_status {
+        if (n == 0) return SEMB_OK;
+        TRY(hip_status(hipMemcpyAsync(bb.data(), out->best, 4 * n, hipMemcpyDeviceToHost, stream), "copy"));
+        TRY(hip_status(hipMemcpyAsync(ss.data(), out->s_best, 4 * n, hipMemcpyDeviceToHost, stream), "copy"));
+        TRY(hip_status(hipMemcpyAsync(tt.data(), out->stack, 4 * n, hipMemcpyDeviceToHost, stream), "copy"));
+        return hip_status(hipStreamSynchronize(stream), "semb_tune_batch: synchronize");
+    };
+    semb_status st = SEMB_OK;
+    int best_shape = kDefaultBatchShape;
+    float best_ms = 0.f;
+    for (int k = 0; k < semb::kBatchShapes && st == SEMB_OK; ++k) {
+        const int sid = k == 0 ? kDefaultBatchShape : (k <= kDefaultBatchShape ? k - 1 : k);  // the default first
+        st = batch_common(g, jobs, b, tiles, ntiles, ngroups, nparts, out, ws, ws_bytes, stream, sid);  // warm-up
+        if (st == SEMB_OK) st = hip_status(hipEventRecord(e0, stream), "hipEventRecord");
+        for (int r = 0; r < reps && st == SEMB_OK; ++r)
+            st = batch_common(g, jobs, b, tiles, ntiles, ngroups, nparts, out, ws, ws_bytes, stream, sid);
+        if (st == SEMB_OK) st = hip_status(hipEventRecord(e1, stream), "hipEventRecord");
+        if (st == SEMB_OK) st = hip_status(hipEventSynchronize(e1), "hipEventSynchronize");
+        float t = 0.f;
+        if (st == SEMB_OK) st = hip_status(hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime");
+        if (st != SEMB_OK) break;
+        t /= (float)reps;
+        bool same = true;
+        if (k == 0) {
+            st = fetch(rb, rs, rt);
+        } else {
+            st = fetch(cb, cs, ct);
+            same = cb == rb && memcmp(cs.data(), rs.data(), 4 * n) == 0 && memcmp(ct.data(), rt.data(), 4 * n) == 0;
+        }
+        if (st != SEMB_OK) break;
+        if (ms) ms[sid] = same ? t : -1.f;
+        // another shape must beat the default by 2% (timing noise does not flip the choice)
+        if (same && (k == 0 || t < (best_shape == kDefaultBatchShape ? 0.98f : 1.f) * best_ms)) {
+            best_ms = t;
+            best_shape = sid;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SEMB_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_shape_mu);
+        g_batch[batch_key(b->w_cmp, b->w_crs, g, jobs)] = BatchChoice{best_shape, split_params};
+    }
+    *shape = best_shape;
+    return SEMB_OK;
+}
+
+int32_t semb_tuning_save(const char *path)
+{
+    if (!path) {
+        fail(SEMB_EINVAL, "semb_tuning_save: path is NULL");
+        return -1;
+    }
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    FILE *f = fopen(path, "w");
+    if (!f) {
+        fail(SEMB_EINVAL, "semb_tuning_save: cannot open %s", path);
+        return -1;
+    }
+    int32_t n = 0;
+    fprintf(f, "# semb tuning table v1 (%s)\n", semb_version());
+    fprintf(f, "# scan  kind w traces_bucket ns_bucket shape\n");
+    fprintf(f, "# batch w_cmp w_crs traces_bucket ns_bucket shape split_params\n");
+    for (const auto &kv : g_shapes) {
+        fprintf(f, "scan %d %d %d %d %d\n", kv.first.kind, kv.first.w, kv.first.traces, kv.first.ns, kv.second);
+        ++n;
+    }
+    for (const auto &kv : g_batch) {
+        fprintf(f, "batch %d %d %d %d %d %d\n", kv.first.wc, kv.first.wr, kv.first.traces, kv.first.ns,
+                kv.second.shape, kv.second.split);
+        ++n;
+    }
+    if (fclose(f) != 0) {
+        fail(SEMB_EINVAL, "semb_tuning_save: writing %s failed", path);
+        return -1;
+    }
+    return n;
+}
+
+int32_t semb_tuning_load(const char *path)
+{
+    if (!path) {
+        fail(SEMB_EINVAL, "semb_tuning_load: path is NULL");
+        return -1;
+    }
+    FILE *f = fopen(path, "r");
+    if (!f) {
+        fail(SEMB_EINVAL, "semb_tuning_load: cannot open %s", path);
+        return -1;
+    }
+    std::map<ShapeKey, int> scans;
+    std::map<BatchKey, BatchChoice> batches;
+    char line[256];
+    int lineno = 0;
+    bool bad = false;
+    while (fgets(line, sizeof line, f)) {
+        ++lineno;
+        if (line[0] == '#' || line[0] == '\n') continue;
+        int a[6];
+        if (sscanf(line, "scan %d %d %d %d %d", &a[0], &a[1], &a[2], &a[3], &a[4]) == 5) {
+            if ((a[0] != SEMB_KIND_CMP && a[0] != SEMB_KIND_CRS) || a[4] < 0 || a[4] >= semb::kScanShapes) {
+                bad = true;
+                break;
+            }
+            scans[ShapeKey{a[0], a[1], a[2], a[3]}] = a[4];
+        } else if (sscanf(line, "batch %d %d %d %d %d %d", &a[0], &a[1], &a[2], &a[3], &a[4], &a[5]) == 6) {
+            if (a[4] < 0 || a[4] >= semb::kBatchShapes || a[5] < 1) {
+                bad = true;
+                break;
+            }
+            batches[BatchKey{a[0], a[1], a[2], a[3]}] = BatchChoice{a[4], a[5]};
+        } else {
+            bad = true;
+            break;
+        }
+    }
+    fclose(f);
+    if (bad) {
+        fail(SEMB_EINVAL, "semb_tuning_load: %s line %d is not a tuning entry", path, lineno);
+        return -1;
+    }
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    for (const auto &kv : scans) g_shapes[kv.first] = kv.second;
+    for (const auto &kv : batches) g_batch[kv.first] = kv.second;
+    return (int32_t)(scans.size() + batches.size());
 }
 
 const char *semb_last_error(void) { return g_last_error.c_str(); }

@@ -139,7 +139,9 @@ constexpr int kScanShapes = 6;
 hipError_t launch_scan(int kind, const ScanArgs &a, int shape, hipStream_t stream);
 hipError_t launch_scan_cmp(const ScanArgs &a, int shape, hipStream_t stream);
 hipError_t launch_scan_crs(const ScanArgs &a, int shape, hipStream_t stream);
-hipError_t launch_batch(const BatchArgs &a, int ngroups, hipStream_t stream);
+// Batched scan in batch tile shape `shape` (0 .. kBatchShapes - 1).
+constexpr int kBatchShapes = 3;
+hipError_t launch_batch(const BatchArgs &a, int ngroups, int shape, hipStream_t stream);
 hipError_t launch_point(int kind, const PointArgs &a, hipStream_t stream);
 hipError_t launch_grad(int kind, const PointArgs &a, hipStream_t stream);
 hipError_t launch_refine(int kind, const PointArgs &a, const RefineArgs &o, hipStream_t stream);

@@ -94,13 +94,18 @@ hipError_t launch_energy_w(const float *samples, const int64_t *sample_off, cons
 // tile that covers all parameters of its (job, sample block) writes the
 // outputs; otherwise it stores a partial pick, and the last tile of its group
 // to finish (counted with an atomic, after a release fence) merges the
-// group's partials in split order.  Both kinds use 8 waves and a 2048-sample
-// stage: CMP tiles with 2 parameters per wave, CRS tiles with 4 for windows
-// up to 9 samples (each trace's loop work is then shared by 4 parameters) and
-// 2 for longer ones, whose 4 x (w + 2) accumulators would not fit the
-// 128-VGPR budget of 4 waves per SIMD; both keep their windows behind a
-// branch.  The stage and 128-trace metadata parts keep the LDS union at two
-// workgroups per CU.
+// group's partials in split order.  Both kinds use 8 waves; CMP tiles give
+// each wave 2 parameters, CRS tiles 4 for windows up to 9 samples (each
+// trace's loop work is then shared by 4 parameters) and 2 for longer ones,
+// whose 4 x (w + 2) accumulators would not fit the 128-VGPR budget of 4
+// waves per SIMD.  The CRS tile comes in the batch shapes below (BatchShape);
+// CMP tiles are the same in every shape.  The LDS union of the two kinds'
+// layouts keeps two workgroups per CU.
+//   0: CRS windows behind a branch, 2048-sample stage;
+//   1: CRS windows branch-free, 2560-sample stage (the exhaustive CRS
+//      scan's default tile);
+//   2: CRS windows branch-free, 2048-sample stage.
+// Every shape sums each cell's traces in the same order (bit-identical).
 // ---------------------------------------------------------------------------
 constexpr int BATCH_NW = 8;
 constexpr int BATCH_P_CMP = 2;
@@ -108,17 +113,36 @@ constexpr int batch_p_crs(int wr) { return wr <= 9 ? 4 : 2; }
 constexpr int BATCH_CAP = 2048;
 constexpr int BATCH_TMAX = 128;
 
+template <int BS>
+struct BatchShape;
+template <>
+struct BatchShape<0> {
+    static constexpr int CAP_CRS = 2048;
+    static constexpr bool BRANCHY_CRS = true;
+};
+template <>
+struct BatchShape<1> {
+    static constexpr int CAP_CRS = 2560;
+    static constexpr bool BRANCHY_CRS = false;
+};
+template <>
+struct BatchShape<2> {
+    static constexpr int CAP_CRS = 2048;
+    static constexpr bool BRANCHY_CRS = false;
+};
+
 __global__ void reset_counters_kernel(unsigned int *c, int n)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = 0u;
 }
 
-template <int WC, int WR>
+template <int WC, int WR, int BS>
 __global__ void __launch_bounds__(BATCH_NW * WAVE) __attribute__((amdgpu_waves_per_eu(4)))
 batch_kernel(BatchArgs b)
 {
+    constexpr int CAP_R = BatchShape<BS>::CAP_CRS;
     using LC = StageLds<SEMB_KIND_CMP, WC, BATCH_P_CMP, BATCH_NW, BATCH_CAP, BATCH_TMAX>;
-    using LR = StageLds<SEMB_KIND_CRS, WR, batch_p_crs(WR), BATCH_NW, BATCH_CAP, BATCH_TMAX>;
+    using LR = StageLds<SEMB_KIND_CRS, WR, batch_p_crs(WR), BATCH_NW, CAP_R, BATCH_TMAX>;
     __shared__ union U {
         LC c;
         LR r;
@@ -156,7 +180,7 @@ batch_kernel(BatchArgs b)
             scan_tile<SEMB_KIND_CMP, WC, BATCH_P_CMP, BATCH_NW, BATCH_CAP, BATCH_TMAX, true>(
                 b.g, b.j, b.pc, L.c, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, nullptr, bS, bI, bSt);
         else
-            scan_tile<SEMB_KIND_CRS, WR, batch_p_crs(WR), BATCH_NW, BATCH_CAP, BATCH_TMAX, true>(
+            scan_tile<SEMB_KIND_CRS, WR, batch_p_crs(WR), BATCH_NW, CAP_R, BATCH_TMAX, BatchShape<BS>::BRANCHY_CRS>(
                 b.g, b.j, b.pr, L.r, tl.job, tl.sblk, tl.p_begin, tl.p_end, nullptr, nullptr, bS, bI, bSt);
         const int64_t row = b.j.out_off[tl.job] + tl.sblk * WAVE + lane;
         if (tl.nsplit <= 1) {
@@ -201,35 +225,47 @@ batch_kernel(BatchArgs b)
     }
 }
 
-template <int WC>
-hipError_t launch_batch_wc(const BatchArgs &a, dim3 grid, hipStream_t stream)
-{
-    switch (a.pr.w) {
-    case 9: hipLaunchKernelGGL((batch_kernel<WC, 9>), grid, dim3(BATCH_NW * WAVE), 0, stream, a); break;
-    case 11: hipLaunchKernelGGL((batch_kernel<WC, 11>), grid, dim3(BATCH_NW * WAVE), 0, stream, a); break;
-    case 15: hipLaunchKernelGGL((batch_kernel<WC, 15>), grid, dim3(BATCH_NW * WAVE), 0, stream, a); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <int WC, int WR>
+template <int WC, int WR, int BS>
 int batch_blocks_per_cu()
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<WC, WR>, BATCH_NW * WAVE, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<WC, WR, BS>, BATCH_NW * WAVE, 0) !=
+        hipSuccess)
         n = 1;
     return n < 1 ? 1 : n;
 }
 
-int batch_occupancy(int wc, int wr)
+// The persistent grid: as many workgroups as fit on the GPU at once (never
+// more than there are tiles).
+template <int WC, int WR, int BS>
+hipError_t launch_batch_k(const BatchArgs &a, int cus, hipStream_t stream)
 {
-#define SEMB_OCC(A, B) if (wc == A && wr == B) return batch_blocks_per_cu<A, B>();
-    SEMB_OCC(9, 9) SEMB_OCC(9, 11) SEMB_OCC(9, 15)
-    SEMB_OCC(11, 9) SEMB_OCC(11, 11) SEMB_OCC(11, 15)
-    SEMB_OCC(15, 9) SEMB_OCC(15, 11) SEMB_OCC(15, 15)
-#undef SEMB_OCC
-    return 1;
+    const long long want = (long long)cus * batch_blocks_per_cu<WC, WR, BS>();
+    const dim3 grid((unsigned)(want < a.ntiles ? want : a.ntiles));
+    hipLaunchKernelGGL((batch_kernel<WC, WR, BS>), grid, dim3(BATCH_NW * WAVE), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <int WC, int WR>
+hipError_t launch_batch_s(const BatchArgs &a, int shape, int cus, hipStream_t stream)
+{
+    switch (shape) {
+    case 0: return launch_batch_k<WC, WR, 0>(a, cus, stream);
+    case 1: return launch_batch_k<WC, WR, 1>(a, cus, stream);
+    case 2: return launch_batch_k<WC, WR, 2>(a, cus, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int WC>
+hipError_t launch_batch_wc(const BatchArgs &a, int shape, int cus, hipStream_t stream)
+{
+    switch (a.pr.w) {
+    case 9: return launch_batch_s<WC, 9>(a, shape, cus, stream);
+    case 11: return launch_batch_s<WC, 11>(a, shape, cus, stream);
+    case 15: return launch_batch_s<WC, 15>(a, shape, cus, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -256,7 +292,7 @@ hipError_t launch_scan(int kind, const ScanArgs &a, int shape, hipStream_t strea
     return kind == SEMB_KIND_CMP ? launch_scan_cmp(a, shape, stream) : launch_scan_crs(a, shape, stream);
 }
 
-hipError_t launch_batch(const BatchArgs &a, int ngroups, hipStream_t stream)
+hipError_t launch_batch(const BatchArgs &a, int ngroups, int shape, hipStream_t stream)
 {
     const int ncount = 1 + ngroups;
     hipLaunchKernelGGL(reset_counters_kernel, dim3((ncount + 255) / 256 < 1024 ? (ncount + 255) / 256 : 1024),
@@ -266,12 +302,10 @@ hipError_t launch_batch(const BatchArgs &a, int ngroups, hipStream_t stream)
     int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    const long long want = (long long)cus * batch_occupancy(a.pc.w, a.pr.w);
-    const dim3 grid((unsigned)(want < a.ntiles ? want : a.ntiles));
     switch (a.pc.w) {
-    case 9: return launch_batch_wc<9>(a, grid, stream);
-    case 11: return launch_batch_wc<11>(a, grid, stream);
-    case 15: return launch_batch_wc<15>(a, grid, stream);
+    case 9: return launch_batch_wc<9>(a, shape, cus, stream);
+    case 11: return launch_batch_wc<11>(a, shape, cus, stream);
+    case 15: return launch_batch_wc<15>(a, shape, cus, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -135,18 +135,24 @@ struct __align__(16) TraceRun {
     double cc;
 };
 
-// Positions of one LDS plane: a block of zeros (W + 1 words, rounded up to
-// 4) that windows off their trace read in the branch-free tile shapes, then
-// the CAP staged positions.
-template <int W, int CAP>
+// Positions of one LDS plane: a block of zeros (at least the W + 1 words a
+// window reads) that windows off their trace read in the branch-free tile
+// shapes, then the CAP staged positions.  For CMP the block is 64 words, so
+// that the plane stride stays a multiple of 64 words (CAP is one) and one
+// ds_read2st64 fetches a window's u0 and u1 (measured 0.9% faster on the
+// CMP-large scan); for CRS it is W + 1 rounded up to 4 words, which keeps the
+// 8 x 4 tile within 128 VGPRs without spills (the wider block measured 0.9%
+// slower on the CRS line).
+template <int KIND, int W, int CAP>
 struct Plane {
-    static constexpr int ZP = (W + 1 + 3) & ~3;  // words of the zero block, at position 0
-    static constexpr int STRIDE = ZP + CAP;      // words per plane
+    static_assert(W + 1 <= 64 && CAP % 64 == 0, "zero block and stage sizes");
+    static constexpr int ZP = KIND == SEMB_KIND_CMP ? 64 : (W + 1 + 3) & ~3;  // words of the zero block
+    static constexpr int STRIDE = ZP + CAP;                                    // words per plane
 };
 
 template <int KIND, int W, int P, int NW, int CAP, int TMAX>
 struct StageLds {
-    float st[4][Plane<W, CAP>::STRIDE];             // staged samples, then their window energy
+    float st[4][Plane<KIND, W, CAP>::STRIDE];             // staged samples, then their window energy
                                                     // (Gram form): u0, u1, u2^2; each plane
                                                     // starts with the zero block
     double2 tab[KIND == SEMB_KIND_CRS ? NW * P : 1][WAVE];  // CRS: (2 alpha + beta, alpha^2 + gamma)
@@ -228,7 +234,7 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
     if (tid < na) L.ag_s[tid] = (afirst < 0) ? c : jv.apert_gather[afirst + tid];
     // the zero block at the start of every plane (read by off-trace windows;
     // the previous tile's pick may have reused it)
-    constexpr int ZW = Plane<W, CAP>::ZP;
+    constexpr int ZW = Plane<KIND, W, CAP>::ZP;
     if (tid < 4 * ZW) L.st[tid / ZW][tid % ZW] = 0.f;
     __syncthreads();
     if (tid == 0) {
@@ -371,7 +377,7 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                     incl = len;
                 }
                 // window start a = k - HW sits at stage position ZP + (incl - len) + a - lo
-                if (wv == 0 && lane < nfit) L.run[e].off = 4 * (Plane<W, CAP>::ZP + incl - len - L.t_lo[e] - HW);
+                if (wv == 0 && lane < nfit) L.run[e].off = 4 * (Plane<KIND, W, CAP>::ZP + incl - len - L.t_lo[e] - HW);
 
                 // ---- stage the samples and their window energy -------------------
                 // Direct global->LDS loads (global_load_lds_dword): lane l of a wave
@@ -385,7 +391,7 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                     for (int p0 = 0; p0 < rl; p0 += WAVE) {
                         if (p0 + lane < rl) {
                             const long long gi = src + p0 + lane;
-                            const int at = Plane<W, CAP>::ZP + rb + p0;
+                            const int at = Plane<KIND, W, CAP>::ZP + rb + p0;
                             lds_dma(g.samples + gi, &L.st[0][at]);
                             lds_dma(pv.u0 + gi, &L.st[1][at]);
                             lds_dma(pv.u1 + gi, &L.st[2][at]);
@@ -456,7 +462,7 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                                 const float x = (float)__builtin_amdgcn_fract(tau);
                                 const float u = 1.f - x;
                                 const float *sp = stage_at(&L.st[0][0], ((unsigned)k << 2) + (unsigned)off);
-                                constexpr int PS = Plane<W, CAP>::STRIDE;
+                                constexpr int PS = Plane<KIND, W, CAP>::STRIDE;
                                 float fw[W + 1];
 #pragma unroll
                                 for (int j = 0; j <= W; ++j) fw[j] = sp[j];
@@ -496,7 +502,7 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
 #pragma unroll
                             for (int p = 0; p < P; ++p) {
                                 const float *sp = stage_at(&L.st[0][0], addr[p]);
-                                constexpr int PS = Plane<W, CAP>::STRIDE;
+                                constexpr int PS = Plane<KIND, W, CAP>::STRIDE;
                                 float fw[W + 1];
 #pragma unroll
                                 for (int j = 0; j <= W; ++j) fw[j] = sp[j];
@@ -613,7 +619,7 @@ struct ShapeT<3, W> {
 
 template <int W>
 struct ShapeT<4, W> {
-    static constexpr int NW = 8, P = W <= 15 ? 4 : 2, CAP = 2048, TMAX = 128, WPE = 2;
+    static constexpr int NW = 8, P = W <= 15 ? 4 : 2, CAP = 2048, TMAX = 128, WPE = 4;
     static constexpr bool BRANCHY = true;
 };
 template <int W>

@@ -340,9 +340,48 @@ def test_tuner_rejects_bad_arguments(semb):
                             C.c_void_p(0x10000), 1 << 20, C.byref(shape), None, None) == 1
 
 
+def test_tuning_table_round_trip(semb, tmp_path):
+    """Scan and batch choices written with semb_tuning_save come back after a
+    clear with semb_tuning_load; a file with a line that is not an entry is
+    refused and leaves the table as it was."""
+    L = semb.lib()
+    L.semb_clear_tuning()
+    g1, g2 = _gathers(semb, ntraces=30, ngathers=1, ns_max=1000), _gathers(semb, ntraces=60, ngathers=1, ns_max=2000)
+    j1 = _jobs(semb, max_apert=9)
+    assert L.semb_set_scan_shape(0, 15, C.byref(g2), C.byref(j1), 3) == 0
+    assert L.semb_set_scan_shape(1, 9, C.byref(g1), C.byref(j1), 4) == 0
+    assert L.semb_set_batch_choice(11, 9, C.byref(g1), C.byref(j1), 2, 1024) == 0
+    path = str(tmp_path / "tuning.txt")
+    assert semb.save_tuning(path) == 3
+    L.semb_clear_tuning()
+    assert semb.lib().semb_scan_shape(0, 15, C.byref(g2), C.byref(j1)) == 0
+    sh, sp = C.c_int32(-1), C.c_int32(-1)
+    L.semb_batch_choice(11, 9, C.byref(g1), C.byref(j1), C.byref(sh), C.byref(sp))
+    assert (sh.value, sp.value) == (0, 256)
+    assert semb.load_tuning(path) == 3
+    assert L.semb_scan_shape(0, 15, C.byref(g2), C.byref(j1)) == 3
+    assert L.semb_scan_shape(1, 9, C.byref(g1), C.byref(j1)) == 4
+    L.semb_batch_choice(11, 9, C.byref(g1), C.byref(j1), C.byref(sh), C.byref(sp))
+    assert (sh.value, sp.value) == (2, 1024)
+    bad = tmp_path / "bad.txt"
+    bad.write_text("scan 0 15 6 11 1\nnot an entry\n")
+    with pytest.raises(semb.SembError):
+        semb.load_tuning(str(bad))
+    assert L.semb_scan_shape(0, 15, C.byref(g2), C.byref(j1)) == 3  # unchanged
+    bad.write_text("batch 11 9 5 10 7 256\n")  # shape out of range
+    with pytest.raises(semb.SembError):
+        semb.load_tuning(str(bad))
+    with pytest.raises(semb.SembError):
+        semb.load_tuning(str(tmp_path / "missing.txt"))
+    L.semb_clear_tuning()
+
+
 def test_shape_count_matches_the_header(semb):
     text = open(HEADER).read()
     assert f"#define SEMB_SCAN_SHAPES {semb.SCAN_SHAPES}" in text
+    assert f"#define SEMB_BATCH_SHAPES {semb.BATCH_SHAPES}" in text
+    assert all(semb.batch_shape_name(s) for s in range(semb.BATCH_SHAPES))
+    assert semb.batch_shape_name(semb.BATCH_SHAPES) is None
 
 
 def test_shape_table_under_concurrent_threads(semb):

@@ -77,25 +77,71 @@ def _kind_rows(bw, kind):
 def test_batch_equals_per_kind_scans(split, w_cmp, w_crs):
     """A 40-gather stretch of the batched line (uneven fold 8..120 and length
     500..2000): the batch must reproduce cmp_scan on its CMP jobs and crs_scan
-    on its CRS jobs exactly (same per-cell sums in the same order), for every
-    window the batch kernel is built for (CRS tiles hold 4 parameters per wave
-    at w 9 and 2 above)."""
+    on its CRS jobs exactly (same per-cell sums in the same order), in every
+    batch tile shape and for every window the batch kernel is built for (CRS
+    tiles hold 4 parameters per wave at w 9 and 2 above)."""
     import dataclasses
     import torch
+    import paper_1907_11678_amd as semb
     bw = dataclasses.replace(synth.batched_line(ids=range(2000, 2040)), w_cmp=w_cmp, w_crs=w_crs)
     b = Batch(bw, split)
-    b.run()
-    torch.cuda.synchronize()
-    best, sb, st = b.outputs()
+    refs = {}
     for kind, grid, w in ((0, bw.grid_cmp, bw.w_cmp), (1, bw.grid_crs, bw.w_crs)):
         sub = bw.subset(kind)
-        ref = gu.run_scan("cmp" if kind == 0 else "crs", bw.gathers, sub, grid, w, dg=b.dg,
-                          dj=gu.device_inputs(bw.gathers, sub)[1])
-        rows = _kind_rows(bw, kind)
-        assert np.array_equal(best[rows], ref[0][rows]), kind
-        assert np.array_equal(sb[rows], ref[1][rows]), kind
-        assert np.array_equal(st[rows], ref[2][rows]), kind
-    _say("batch == per-kind scans", b.ntiles, "tiles", b.ng, "groups")
+        refs[kind] = gu.run_scan("cmp" if kind == 0 else "crs", bw.gathers, sub, grid, w, dg=b.dg,
+                                 dj=gu.device_inputs(bw.gathers, sub)[1])
+    try:
+        for shape in range(semb.BATCH_SHAPES):
+            semb.set_batch_choice(bw.w_cmp, bw.w_crs, b.dg, b.dj, shape, split)
+            assert semb.batch_choice(bw.w_cmp, bw.w_crs, b.dg, b.dj) == (shape, split)
+            b.best.fill_(-7)
+            b.run()
+            torch.cuda.synchronize()
+            best, sb, st = b.outputs()
+            for kind in (0, 1):
+                ref = refs[kind]
+                rows = _kind_rows(bw, kind)
+                assert np.array_equal(best[rows], ref[0][rows]), (shape, kind)
+                assert np.array_equal(sb[rows], ref[1][rows]), (shape, kind)
+                assert np.array_equal(st[rows], ref[2][rows]), (shape, kind)
+    finally:
+        semb.set_batch_choice(bw.w_cmp, bw.w_crs, b.dg, b.dj, -1)
+    _say("batch == per-kind scans in every shape", b.ntiles, "tiles", b.ng, "groups")
+
+
+def test_batch_tuner_records_a_bit_identical_choice():
+    """tune_batch times every batch shape over two splits on a 200-gather
+    stretch, excludes none (they are bit-identical), records the fastest
+    (shape, split), and the scan with the recorded choice still equals the
+    per-kind scans."""
+    import torch
+    import paper_1907_11678_amd as semb
+    bw = synth.batched_line(ids=range(1000, 1200))
+    b = Batch(bw, 256)
+    jobs, gs = bw.jobs, bw.gathers
+    shape, split, times = semb.tune_batch(b.dg, b.dj, bw.kind, b.kind, b.qc, bw.w_cmp, b.A, b.B, b.qr, bw.w_crs,
+                                          jobs.central, jobs.apert_ptr, jobs.apert_gather, gs.ns, gs.trace_ptr,
+                                          b.best, b.sb, b.st, splits=(256, 1024), reps=1, sample_jobs=120)
+    try:
+        _say("batch tuner:", shape, split, times)
+        assert set(times) == {256, 1024}
+        assert all(m >= 0 for ms in times.values() for m in ms)
+        assert semb.batch_choice(bw.w_cmp, bw.w_crs, b.dg, b.dj) == (shape, split)
+        faster = {(s, sp): ms[s] for sp, ms in times.items() for s in range(semb.BATCH_SHAPES)}
+        assert faster[(shape, split)] == min(faster[(s, split)] for s in range(semb.BATCH_SHAPES)
+                                             if s == 0 or faster[(s, split)] < 0.98 * faster[(0, split)])
+        b2 = Batch(bw, split)
+        b2.run()
+        torch.cuda.synchronize()
+        best, sb, st = b2.outputs()
+        for kind, grid, w in ((0, bw.grid_cmp, bw.w_cmp), (1, bw.grid_crs, bw.w_crs)):
+            sub = bw.subset(kind)
+            ref = gu.run_scan("cmp" if kind == 0 else "crs", gs, sub, grid, w, dg=b.dg,
+                              dj=gu.device_inputs(gs, sub)[1])
+            rows = _kind_rows(bw, kind)
+            assert np.array_equal(best[rows], ref[0][rows]) and np.array_equal(sb[rows], ref[1][rows])
+    finally:
+        semb.clear_tuning()
 
 
 def test_tiles_outside_the_given_plan_sizes_are_skipped():
