@@ -48,7 +48,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 vector peak (published)
+# LDS: 128 bytes per clock per CU, 256 CUs, 2.4 GHz
+PEAK_LDS_TBPS = 128 * 256 * 2.4e9 / 1e12
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "scan_kernel_cmp_large_traffic.txt")
+COUNTER_RECORD = os.path.join(ROOT, "profiles", "scan_kernel_counters.txt")
 
 
 def log(*a):
@@ -58,6 +61,53 @@ def log(*a):
 def eq2_flops(evals: int, valid: int, w: int) -> int:
     """Eq. 2 work: 12 per intersection, 7w per window on its trace."""
     return 12 * evals + 7 * w * valid
+
+
+def roofline(kernel: str, evals: int, valid: int, w: int, kernel_ms: float, call_ms: float | None,
+             traffic=None, flops: int | None = None, work: str | None = None) -> dict:
+    """The roofline object of one leg's dominant kernel.
+
+    achieved = Eq. (2)'s work (12 flops per intersection, 7w per contributing
+    window) / the kernel's mean launch time (HIP events around its launches),
+    against the FP32 vector peak.  This counts the paper's per-intersection
+    work, not the instructions issued: the kernels form a window's energy from
+    a precomputed Gram form, so a window costs them 2w + 3 FP32 FMAs, not 7w.
+    frac_whole_call divides by the whole call instead (window-energy pre-pass
+    included).  With a counter record of the same kernel sources (profiles/),
+    also the executed rates from the counters, at the live kernel time:
+    FP32 FMA work against the FP32 peak, VALU instructions per CU clock (at
+    2.4 GHz), and LDS bytes read against the LDS peak."""
+    from paper_1907_11678_amd import profiling
+    if flops is None:
+        flops = eq2_flops(evals, valid, w)
+    t = kernel_ms * 1e-3
+    ach = flops / t / 1e12
+    out = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+           "frac": ach / PEAK_FP32_TFLOPS, "traffic": traffic, "kernel": kernel,
+           "work": work or "Eq. (2) flops: 12 per intersection + 7w per contributing window",
+           "evals_per_launch": evals, "valid_windows_per_launch": valid, "flops_per_launch": flops,
+           "avg_launch_ms": kernel_ms,
+           "timed": "avg_launch_ms is the kernel alone; frac_whole_call also counts the window-energy pass"}
+    if call_ms:
+        out["call_ms"] = call_ms
+        out["frac_whole_call"] = flops / (call_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS
+    rec = profiling.current_counters(COUNTER_RECORD, kernel)
+    if rec is not None:
+        we = evals / 64.0
+        fma = rec["fma_f32_per_wave_eval"] * we * 64 * 2 / t / 1e12
+        lds = rec["lds_load_bytes_per_lane_eval"] * evals / t / 1e12
+        issue = rec["valu_insts_per_wave_eval"] * we / (t * 2.4e9 * 256)
+        out["executed"] = {
+            "fp32_fma_tflops": fma, "fp32_fma_frac": fma / PEAK_FP32_TFLOPS,
+            "valu_insts_per_wave_eval": rec["valu_insts_per_wave_eval"],
+            "valu_insts_per_clk_per_cu": issue,
+            "lds_tbps": lds, "lds_peak_tbps": PEAK_LDS_TBPS, "lds_frac": lds / PEAK_LDS_TBPS,
+            "lds_busy_fraction": rec.get("lds_busy_fraction"),
+            "binding": "lds" if lds / PEAK_LDS_TBPS > issue else "valu issue",
+            "source": os.path.relpath(COUNTER_RECORD, ROOT)}
+    else:
+        out["executed"] = None
+    return out
 
 
 def cmp_valid_evals(h: np.ndarray, q: np.ndarray, ns: int, dt: float, w: int) -> int:
@@ -76,52 +126,75 @@ def cmp_valid_evals(h: np.ndarray, q: np.ndarray, ns: int, dt: float, w: int) ->
     return int(np.maximum(smax - smin + 1, 0).sum())
 
 
-def _count_open(r1, r2, n):
-    """Integers s in [0, n-1] with r1 < s < r2 (elementwise; empty where r1 >= r2)."""
-    lo = np.maximum(np.floor(r1) + 1, 0)
-    hi = np.minimum(np.ceil(r2) - 1, n - 1)
-    return np.maximum(hi - lo + 1, 0)
-
-
-def crs_valid_fraction(gs, jobs, grid, w: int, js) -> float:
-    """Fraction of the intersections of jobs `js` whose window lies on the
-    trace.  With u(s) = T/dt^2 = s^2 + beta s + gamma (convex in s), a trace
-    contributes at s iff hw^2 <= u(s) < (ns_i - 1 - hw)^2, i.e. s lies in the
-    root interval of the upper bound minus that of the lower bound."""
-    hw = (w - 1) // 2
-    dt = gs.dt
-    A = grid.A.astype(np.float64)[:, None, None]
-    B = grid.B.astype(np.float64)[None, :, None]
-    q = grid.q.astype(np.float64)[None, None, :]
-    valid = total = 0.0
+def _aperture_traces(gs, jobs, kind):
+    """Per (job, aperture trace): job index, trace index, the trace's gather."""
     tp = gs.trace_ptr.astype(np.int64)
-    for j in js:
-        c = int(jobs.central[j])
-        n = int(gs.ns[c])
-        for g in jobs.apert_gather[jobs.apert_ptr[j]:jobs.apert_ptr[j + 1]]:
-            for i in range(tp[g], tp[g + 1]):
-                dm = float(gs.midpoint[i]) - float(gs.central_x[c])
-                h = float(gs.half_offset[i])
-                beta = (4 * A * dm + 2 * B * dm * dm) / dt
-                gamma = (4 * A * A * dm * dm + q * h * h) / (dt * dt)
-                beta, gamma = np.broadcast_arrays(beta, gamma)
-                top = float(gs.ns[g] - 1 - hw)
+    if kind == "crs":
+        ap = np.asarray(jobs.apert_ptr, np.int64)
+        pj = np.repeat(np.arange(jobs.njobs), np.diff(ap))
+        pg = np.asarray(jobs.apert_gather, np.int64)[: int(ap[-1])]
+    else:
+        pj = np.arange(jobs.njobs)
+        pg = np.asarray(jobs.central, np.int64)
+    cnt = tp[pg + 1] - tp[pg]
+    first = np.cumsum(cnt) - cnt
+    tj = np.repeat(pj, cnt)
+    tg = np.repeat(pg, cnt)
+    ti = np.repeat(tp[pg], cnt) + (np.arange(int(cnt.sum())) - np.repeat(first, cnt))
+    return tj, ti, tg
 
-                def roots(level):
-                    disc = beta * beta - 4 * (gamma - level)
-                    sq = np.sqrt(np.maximum(disc, 0))
-                    r1 = np.where(disc > 0, (-beta - sq) / 2, 0.0)
-                    r2 = np.where(disc > 0, (-beta + sq) / 2, 0.0)
-                    return r1, r2
 
-                u1, u2 = roots(top * top)
-                cnt = _count_open(u1, u2, n)
-                if hw > 0:
-                    l1, l2 = roots(float(hw * hw))
-                    cnt = cnt - _count_open(l1, l2, n)
-                valid += float(cnt.sum())
-                total += float(n) * cnt.size
-    return valid / total
+def valid_windows(gs, jobs, grid, w: int, kind: str, device: str = "cpu", chunk: int = 1 << 25) -> int:
+    """Exact number of (job, t0, parameter, trace) intersections whose window
+    lies on its trace.  With u(s) = T/dt^2 = s^2 + beta s + gamma (convex in s;
+    CMP: beta = 0, gamma = q h^2/dt^2; CRS: beta = (4 A dm + 2 B dm^2)/dt,
+    gamma = (4 A^2 dm^2 + q h^2)/dt^2) a trace contributes at output sample s
+    iff hw^2 <= u(s) < (ns_i - 1 - hw)^2, so for each (trace, parameter) the
+    count is the number of integers of [0, ns_c - 1] in the root interval of
+    the upper level minus those in the root interval of the lower one.  FP64,
+    in chunks of (trace, parameter) pairs, on `device` (torch)."""
+    import torch
+    hw = (w - 1) // 2
+    dt = float(gs.dt)
+    tj, ti, tg = _aperture_traces(gs, jobs, kind)
+    cen = np.asarray(jobs.central, np.int64)[tj]
+    if kind == "crs":
+        dm = gs.midpoint[ti].astype(np.float64) - gs.central_x[cen].astype(np.float64)
+        A = grid.A.astype(np.float64)
+        B = grid.B.astype(np.float64)
+    else:
+        dm = np.zeros(ti.size)
+        A = np.zeros(1)
+        B = np.zeros(1)
+    h = gs.half_offset[ti].astype(np.float64)
+    top = (gs.ns[tg].astype(np.float64) - 1 - hw) ** 2
+    n = gs.ns[cen].astype(np.float64)
+    dev = torch.device(device)
+    f64 = dict(dtype=torch.float64, device=dev)
+    tA = torch.tensor(A, **f64).view(1, -1, 1, 1)
+    tB = torch.tensor(B, **f64).view(1, 1, -1, 1)
+    tq = torch.tensor(grid.q.astype(np.float64), **f64).view(1, 1, 1, -1)
+    npar = A.size * B.size * grid.q.size
+    rows = max(1, chunk // npar)
+    total = 0
+    for r0 in range(0, ti.size, rows):
+        sl = slice(r0, min(r0 + rows, ti.size))
+        d = torch.tensor(dm[sl], **f64).view(-1, 1, 1, 1)
+        hh = torch.tensor(h[sl], **f64).view(-1, 1, 1, 1)
+        nn = torch.tensor(n[sl], **f64).view(-1, 1, 1, 1)
+        beta = (4.0 * tA * d + 2.0 * tB * d * d) / dt
+        gamma = (4.0 * tA * tA * d * d + tq * hh * hh) / (dt * dt)
+
+        def below(level):  # integers s in [0, n-1] with u(s) < level
+            disc = beta * beta - 4.0 * (gamma - level)
+            sq = torch.sqrt(torch.clamp(disc, min=0.0))
+            lo = torch.clamp(torch.floor((-beta - sq) / 2) + 1, min=0.0)
+            hi = torch.minimum(torch.ceil((-beta + sq) / 2) - 1, nn - 1)
+            return torch.where(disc > 0, torch.clamp(hi - lo + 1, min=0.0), torch.zeros_like(disc))
+
+        cnt = below(torch.tensor(top[sl], **f64).view(-1, 1, 1, 1)) - below(float(hw * hw))
+        total += int(cnt.sum().item())
+    return total
 
 
 def main():
@@ -131,8 +204,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cmp-only", action="store_true", help="skip the CRS, batched and refinement legs")
-    ap.add_argument("--legs", default="crs,refine,batched",
-                    help="legs to run after the CMP step (comma list of crs, refine, batched)")
+    ap.add_argument("--legs", default="cmp_plain,crs,refine,batched",
+                    help="legs to run after the CMP step (comma list of cmp_plain, crs, refine, batched)")
     ap.add_argument("--gathers", type=int, default=20000, help="(testing only) fewer CMP gathers")
     ap.add_argument("--cpu-gathers", type=int, default=384, help="CMP gathers in the CPU oracle sample")
     ap.add_argument("--paper-shapes", action="store_true",
@@ -190,7 +263,6 @@ def main():
 
     evals = G * NS * q_host.size * F
     valid = cmp_valid_evals(h, q_host, NS, gs.dt, W)
-    flops = eq2_flops(evals, valid, W)
 
     # tile shape: tuned on the first 1024 midpoints (outside the timed region)
     shape, shape_ms = semb.tune_scan(0, dg, dj, q, W, best, sb, st, ws, sample_jobs=1024, reps=2,
@@ -213,11 +285,12 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = evals / (wall / args.steps)
     k_avg = sum(kt.ms) / len(kt.ms) * 1e-3
-    achieved = flops / k_avg / 1e12
     # the record holds the full workload's per-launch bytes: a reduced run has none
     traffic = profiling.current_traffic(TRAFFIC_RECORD) if full_size else None
+    rl = roofline(f"scan_kernel<0, 15, {shape}>", evals, valid, W, k_avg * 1e3, ms_per_step, traffic)
+    rl["algorithmic_bytes_per_launch"] = 4 * (gs.samples.size + h.size + 3 * n)
     log(f"cmp_large: {ms_per_step:.1f} ms/step, scan kernel {[round(x, 1) for x in kt.ms]} ms, "
-        f"{value:.3e} evals/s, valid fraction {valid / evals:.4f}, {achieved:.1f} TFLOP/s")
+        f"{value:.3e} evals/s, valid fraction {valid / evals:.4f}, {rl['achieved']:.1f} TFLOP/s")
 
     out = {
         "metric": "semblance evals/s (trace-samples x params / s), CMP scan",
@@ -239,18 +312,7 @@ def main():
             "evals_per_step": evals, "valid_windows_per_step": valid,
             "tile_shape": shape, "tile_shape_ms_on_sample": shape_ms,
         },
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": traffic,
-            "kernel": f"scan_kernel<CMP, w=15, shape {shape}>",
-            "flops_per_launch": flops,
-            "avg_launch_ms": k_avg * 1e3,
-            "algorithmic_bytes_per_launch": 4 * (gs.samples.size + h.size + 3 * n),
-        },
+        "roofline": rl,
     }
     # PCIe context (never `value`): the samples' host-to-device copy from pinned
     # memory, timed on its own after the step, and the rate a caller who
@@ -271,6 +333,8 @@ def main():
     torch.cuda.empty_cache()
 
     legs = set() if args.cmp_only else {x.strip() for x in args.legs.split(",") if x.strip()}
+    if "cmp_plain" in legs:
+        out["cmp_plain"] = cmp_plain_leg(torch, synth, semb, dev, stream)
     if legs & {"crs", "refine"}:
         out["crs"], fine = crs_leg(torch, synth, semb, dev, stream)
         if "refine" in legs:
@@ -329,6 +393,51 @@ def _timed_replays(torch, g, stream, n):
     return [e0.elapsed_time(e1) for e0, e1 in ev]
 
 
+def cmp_plain_leg(torch, synth, semb, dev, stream, launches: int = 20):
+    """64 midpoints x fold 24 x 1000 samples (dt 4 ms), 101 velocities, w 11:
+    a call of about a tenth of a millisecond, so `launches` back-to-back
+    cmp_scan calls are captured in one HIP graph and replayed; time per call =
+    replay time / launches."""
+    wl = synth.cmp_plain()
+    gs, jobs = wl.gathers, wl.jobs
+    dg = semb.upload_gathers(gs.samples, gs.sample_off, gs.trace_ptr, gs.ns, gs.half_offset, gs.midpoint,
+                             gs.central_x, gs.dt, device=dev)
+    dj = semb.upload_jobs(jobs.central, None, None, jobs.out_off, jobs.n_out, device=dev)
+    n = jobs.n_out
+    best = torch.empty(n, dtype=torch.int32, device=dev)
+    sb = torch.empty(n, dtype=torch.float32, device=dev)
+    st = torch.empty(n, dtype=torch.float32, device=dev)
+    ws = semb.alloc_workspace(dg.nsamples)
+    q = torch.from_numpy(wl.grid.q).to(dev)
+    s = torch.cuda.Stream()
+    shape, _ = semb.tune_scan(0, dg, dj, q, wl.w, best, sb, st, ws, sample_jobs=64, reps=5, stream=s)
+    with semb.KernelTimer(launches) as kt:
+        for _ in range(launches):
+            semb.cmp_scan(dg, dj, q, wl.w, best, sb, st, ws, stream=s)
+        torch.cuda.synchronize()
+    k_ms = sorted(kt.ms)[len(kt.ms) // 2]
+    s.wait_stream(stream)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for _ in range(launches):
+            semb.cmp_scan(dg, dj, q, wl.w, best, sb, st, ws, stream=s)
+    g.replay()
+    torch.cuda.synchronize()
+    reps = sorted(_timed_replays(torch, g, torch.cuda.current_stream(), 5))
+    call_ms = reps[len(reps) // 2] / launches
+    evals = synth.count_evals(gs, jobs, wl.grid)
+    valid = cmp_valid_evals(gs.half_offset, wl.grid.q, int(gs.ns[0]), gs.dt, wl.w)
+    rl = roofline(f"scan_kernel<0, 11, {shape}>", evals, valid, wl.w, k_ms, call_ms)
+    log(f"cmp_plain: {call_ms * 1e3:.1f} us per call in a {launches}-call graph (scan kernel {k_ms * 1e3:.1f} us "
+        f"eager), {evals / (call_ms * 1e-3):.3e} evals/s, {rl['achieved']:.1f} TFLOP/s")
+    return {"workload": "cmp_plain: 64 midpoints x fold 24 x 1000 samples (dt 4 ms), 101 velocities 1500-4500 m/s, "
+                        "window 11",
+            "value": evals / (call_ms * 1e-3), "unit": "evals/s", "ms_per_call": call_ms,
+            "graph": f"{launches} back-to-back cmp_scan calls per replay, median of 5 replays",
+            "evals": evals, "valid_windows": valid, "kernel_ms_eager_median": k_ms, "tile_shape": shape,
+            "roofline": rl}
+
+
 def crs_leg(torch, synth, semb, dev, stream):
     wl = synth.crs_line()
     cg, cj = wl.gathers, wl.jobs
@@ -353,19 +462,17 @@ def crs_leg(torch, synth, semb, dev, stream):
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / 2
     evals = synth.count_evals(cg, cj, wl.grid)
-    probe = np.linspace(0, cj.njobs - 1, 16).astype(int)
-    vf = crs_valid_fraction(cg, cj, wl.grid, wl.w, probe)
+    valid = valid_windows(cg, cj, wl.grid, wl.w, "crs", device=dev)
     k_ms = sum(kt.ms) / len(kt.ms)
-    tflops = (12 * evals + 7 * wl.w * vf * evals) / (k_ms * 1e-3) / 1e12
+    rl = roofline(f"scan_kernel<1, 9, {shape}>", evals, valid, wl.w, k_ms, wall * 1e3)
     log(f"crs_line: {wall * 1e3:.1f} ms/call, scan kernel {k_ms:.1f} ms, {evals / wall:.3e} evals/s, "
-        f"valid fraction ~{vf:.4f}, {tflops:.1f} TFLOP/s")
+        f"valid fraction {valid / evals:.4f}, {rl['achieved']:.1f} TFLOP/s")
     res = {"workload": "crs_line: 512 centrals, +-4 gathers x fold 30 (270 traces), 1000 samples (dt 4 ms), "
                        "21x21x41 parameters, window 9",
            "value": evals / wall, "unit": "evals/s", "ms_per_call": wall * 1e3, "evals": evals,
-           "kernel_ms": k_ms, "valid_fraction_16_centrals": vf, "tile_shape": shape,
-           "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                        "frac": tflops / PEAK_FP32_TFLOPS, "kernel": f"scan_kernel<CRS, w=9, shape {shape}>"}}
-    fine = {"wl": wl, "dg": dg, "dj": dj, "s_best": sb.cpu().numpy().astype(np.float64), "ms": wall * 1e3}
+           "valid_windows": valid, "kernel_ms": k_ms, "tile_shape": shape, "roofline": rl}
+    fine = {"wl": wl, "dg": dg, "dj": dj, "s_best": sb.cpu().numpy().astype(np.float64), "ms": wall * 1e3,
+            "best": best.cpu().numpy()}
     return res, fine
 
 
@@ -392,6 +499,14 @@ def refine_leg(torch, synth, semb, dev, stream, fine):
 
     s = torch.cuda.Stream()
     shape, _ = semb.tune_scan(1, dg, dj, q, wl.w, best, s0, st0, ws, A=A, B=B, sample_jobs=128, reps=2, stream=s)
+    # the coarse scan's kernel time, eager (it is most of the graph below)
+    with semb.KernelTimer(3) as kt:
+        for _ in range(3):
+            semb.crs_scan(dg, dj, A, B, q, wl.w, best, s0, st0, ws, stream=s)
+        torch.cuda.synchronize()
+    coarse_ms = sum(kt.ms) / len(kt.ms)
+    ev_coarse = synth.count_evals(wl.gathers, wl.jobs, coarse)
+    val_coarse = valid_windows(wl.gathers, wl.jobs, coarse, wl.w, "crs", device=dev)
 
     def run():
         semb.crs_scan(dg, dj, A, B, q, wl.w, best, s0, st0, ws, stream=s)
@@ -416,6 +531,8 @@ def refine_leg(torch, synth, semb, dev, stream, fine):
     d = (Sr - Sf)[sel]
     res = {"workload": "crs_line data, coarse 7x7x11 scan + 8 ascent steps per output sample, one HIP graph",
            "ms": t_ms, "coarse_tile_shape": shape, "exhaustive_ms": fine["ms"], "speedup_vs_exhaustive": fine["ms"] / t_ms,
+           "roofline": roofline(f"scan_kernel<1, 9, {shape}>", ev_coarse, val_coarse, wl.w, coarse_ms, None),
+           "coarse_scan_share_of_graph": coarse_ms / t_ms,
            "rows_compared": int(sel.sum()),
            "s_gap_median": float(np.median(d)), "s_gap_p5": float(np.percentile(d, 5)),
            "frac_at_least_fine": float((d >= -1e-4).mean()),
@@ -425,8 +542,8 @@ def refine_leg(torch, synth, semb, dev, stream, fine):
         f"p5 {res['s_gap_p5']:+.4f}, >= fine-1e-4 on {res['frac_at_least_fine']:.3f} of {int(sel.sum())} rows")
 
     # multi-start: the coarse scan's panel, its 4 best local maxima per row as
-    # starts, 8 steps from each, the best of the four; one graph
-    K = 4
+    # starts, 32 steps from each, the best of the four; one graph
+    K, STEPS_MS = 4, 32
     panel = torch.empty((n, coarse.n), device=dev)
     theta_k = torch.empty((K, n, 3), device=dev)
     s_k = torch.empty((K, n), device=dev)
@@ -440,7 +557,7 @@ def refine_leg(torch, synth, semb, dev, stream, fine):
     def run_ms():
         semb.crs_scan(dg, dj, A, B, q, wl.w, best, s0, st0, ws, panel=panel, stream=s)
         semb.refine_multistart(dg, dj, 1, panel, A, B, q, wl.w, K, theta_k, s_k, st_k, best_k, peak_s, Sm, stm,
-                               thm, steps=8, eta0=0.5, scale=scale, lo=lo, hi=hi, stream=s)
+                               thm, steps=STEPS_MS, eta0=0.5, scale=scale, lo=lo, hi=hi, stream=s)
 
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -454,12 +571,28 @@ def refine_leg(torch, synth, semb, dev, stream, fine):
     torch.cuda.synchronize()
     m_ms = sorted(_timed_replays(torch, gm, torch.cuda.current_stream(), 3))[1]
     dm_ = (Sm.cpu().numpy().astype(np.float64) - Sf)[sel]
-    res["multistart_4"] = {"ms": m_ms, "speedup_vs_exhaustive": fine["ms"] / m_ms,
+    # the rows short of the fine grid by more than 0.01: how far is the fine
+    # grid's optimum from the nearest start, in coarse cells (max over A, B, q)?
+    thf = torch.empty((n, 3), device=dev)
+    semb.theta_from_best(torch.from_numpy(fine["best"]).to(dev), torch.from_numpy(wl.grid.q).to(dev), thf,
+                         A=torch.from_numpy(wl.grid.A).to(dev), B=torch.from_numpy(wl.grid.B).to(dev))
+    th_starts = theta_k.clone()
+    for k in range(K):  # the starts themselves (theta_k now holds the refined ones)
+        semb.theta_from_best(best_k[k], q, th_starts[k], A=A, B=B)
+    torch.cuda.synchronize()
+    sc = np.asarray(scale, np.float64)
+    dist = np.min(np.abs(th_starts.cpu().numpy().astype(np.float64) - thf.cpu().numpy()[None]) / sc, axis=0).max(1)
+    short = (Sm.cpu().numpy().astype(np.float64) - Sf < -0.01) & sel
+    res["multistart_4"] = {"starts": K, "steps": STEPS_MS, "ms": m_ms, "speedup_vs_exhaustive": fine["ms"] / m_ms,
                            "s_gap_median": float(np.median(dm_)), "s_gap_p5": float(np.percentile(dm_, 5)),
-                           "s_gap_mean": float(dm_.mean()), "frac_at_least_fine": float((dm_ >= -1e-4).mean())}
+                           "s_gap_mean": float(dm_.mean()), "frac_at_least_fine": float((dm_ >= -1e-4).mean()),
+                           "rows_short_by_0.01": int(short.sum()),
+                           "short_rows_with_no_start_within_1_coarse_cell": int((short & (dist > 1.0)).sum())}
     res["s_gap_mean"] = float(d.mean())
-    log(f"refine, 4 starts: {m_ms:.1f} ms; S gap median {np.median(dm_):+.4f}, mean {dm_.mean():+.4f}, "
-        f"p5 {np.percentile(dm_, 5):+.4f}")
+    log(f"refine, {K} starts x {STEPS_MS} steps: {m_ms:.1f} ms; S gap median {np.median(dm_):+.4f}, "
+        f"mean {dm_.mean():+.4f}, p5 {np.percentile(dm_, 5):+.4f}, >= fine-1e-4 on {(dm_ >= -1e-4).mean():.3f}; "
+        f"{int(short.sum())} rows short by > 0.01, {int((short & (dist > 1.0)).sum())} of them with no start "
+        f"within one coarse cell of the fine grid's optimum")
     return res
 
 
@@ -472,16 +605,23 @@ def batched_leg(torch, synth, semb, dev, stream):
                              gs.central_x, gs.dt, device=dev)
     dj = semb.upload_jobs(jobs.central, jobs.apert_ptr, jobs.apert_gather, jobs.out_off, jobs.n_out, device=dev)
     kind = torch.from_numpy(bw.kind).to(dev)
-    tiles, ng, npart = semb.batch_plan(bw.kind, jobs.central, jobs.apert_ptr, jobs.apert_gather, gs.ns,
-                                       gs.trace_ptr, bw.grid_cmp.n, bw.grid_crs.n, 256)
-    dtiles = torch.from_numpy(tiles).to(dev)
-    ws = semb.alloc_batch_workspace(dg.nsamples, bw.w_cmp, bw.w_crs, ng, npart)
     qc = torch.from_numpy(bw.grid_cmp.q).to(dev)
     A, B, qr = (torch.from_numpy(x).to(dev) for x in (bw.grid_crs.A, bw.grid_crs.B, bw.grid_crs.q))
     n = jobs.n_out
     best = torch.empty(n, dtype=torch.int32, device=dev)
     sb = torch.empty(n, dtype=torch.float32, device=dev)
     st = torch.empty(n, dtype=torch.float32, device=dev)
+    # batch tile shape and parameter split, tuned on the first 512 jobs (outside the timed region)
+    t = time.time()
+    shape, split, tune_ms = semb.tune_batch(dg, dj, bw.kind, kind, qc, bw.w_cmp, A, B, qr, bw.w_crs, jobs.central,
+                                            jobs.apert_ptr, jobs.apert_gather, gs.ns, gs.trace_ptr, best, sb, st,
+                                            splits=(256, 1024), reps=1, sample_jobs=512, stream=stream)
+    log(f"batch tile shape {shape} ({semb.batch_shape_name(shape)}), split {split}; ms per shape on the "
+        f"512-job sample {tune_ms} ({time.time() - t:.1f} s)")
+    tiles, ng, npart = semb.batch_plan(bw.kind, jobs.central, jobs.apert_ptr, jobs.apert_gather, gs.ns,
+                                       gs.trace_ptr, bw.grid_cmp.n, bw.grid_crs.n, split)
+    dtiles = torch.from_numpy(tiles).to(dev)
+    ws = semb.alloc_batch_workspace(dg.nsamples, bw.w_cmp, bw.w_crs, ng, npart)
     s = torch.cuda.Stream()
 
     def run():
@@ -489,8 +629,9 @@ def batched_leg(torch, synth, semb, dev, stream):
                         stream=s)
 
     s.wait_stream(stream)
-    with semb.KernelTimer(1) as kt:
+    with semb.KernelTimer(2) as kt:
         with torch.cuda.stream(s):
+            run()
             run()
         torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
@@ -503,13 +644,23 @@ def batched_leg(torch, synth, semb, dev, stream):
     ev_c = synth.count_evals(gs, bw.subset(0), bw.grid_cmp)
     ev_r = synth.count_evals(gs, bw.subset(1), bw.grid_crs)
     ev = ev_c + ev_r
-    log(f"batched: graph {t_ms:.1f} ms (kernel {kt.ms[0]:.1f} ms eager), {ev / (t_ms * 1e-3):.3e} evals/s, "
-        f"{tiles.shape[0]} tiles")
+    va_c = valid_windows(gs, bw.subset(0), bw.grid_cmp, bw.w_cmp, "cmp", device=dev)
+    va_r = valid_windows(gs, bw.subset(1), bw.grid_crs, bw.w_crs, "crs", device=dev)
+    k_ms = sum(kt.ms) / len(kt.ms)
+    # one launch does both kinds: Eq. (2) work of each at its own window
+    fl = eq2_flops(ev_c, va_c, bw.w_cmp) + eq2_flops(ev_r, va_r, bw.w_crs)
+    rl = roofline(f"batch_kernel<{bw.w_cmp}, {bw.w_crs}, {shape}>", ev, va_c + va_r, 0, k_ms, t_ms, flops=fl,
+                  work="Eq. (2) flops: 12 per intersection + 7w per contributing window, w 11 for the CMP "
+                       "jobs and 9 for the CRS jobs")
+    log(f"batched: graph {t_ms:.1f} ms (kernel {k_ms:.1f} ms eager), {ev / (t_ms * 1e-3):.3e} evals/s, "
+        f"{tiles.shape[0]} tiles, {rl['achieved']:.1f} TFLOP/s")
     return {"workload": "batched_line: 4096 gathers, fold 8-120, 500-2000 samples (dt 4 ms); 2867 CMP jobs "
                         "(101 velocities, w 11) + 1229 CRS jobs (11x11x21, +-2 gathers, w 9); one persistent "
                         "launch in a HIP graph",
-            "value": ev / (t_ms * 1e-3), "unit": "evals/s", "graph_ms": t_ms, "kernel_ms_eager": kt.ms[0],
-            "evals": ev, "evals_cmp": ev_c, "evals_crs": ev_r, "tiles": int(tiles.shape[0])}
+            "value": ev / (t_ms * 1e-3), "unit": "evals/s", "graph_ms": t_ms, "kernel_ms_eager": k_ms,
+            "evals": ev, "evals_cmp": ev_c, "evals_crs": ev_r, "valid_windows_cmp": va_c, "valid_windows_crs": va_r,
+            "tiles": int(tiles.shape[0]), "batch_shape": shape, "split_params": split,
+            "tuning_ms_per_shape_on_512_jobs": {str(k): v for k, v in tune_ms.items()}, "roofline": rl}
 
 
 def _scan_rate(torch, semb, wl, dev, stream, tune_jobs):

@@ -14,6 +14,12 @@ record of a kernel.
         `rocprofv3 --pmc` runs, and the instruction counts per 64-lane
         evaluation, LDS busy fraction and wave wait fraction.
 
+    python -m paper_1907_11678_amd.profiling counter-record <out.txt> <kernel>=<evals> ... -- <csv> ...
+        The per-evaluation rates of each kernel (VALU and FP32-FMA
+        instructions, LDS instructions and bytes read, LDS busy fraction,
+        waits) from `rocprofv3 --pmc` runs, with the source digest; bench.py
+        reports executed VALU and LDS rates from it while the digest matches.
+
     python -m paper_1907_11678_amd.profiling traffic <fetch_csv> <write_csv>
             <kernel-substring> <copy-bytes> <out.txt>
         Reduce two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs
@@ -36,7 +42,8 @@ from collections import defaultdict
 PKG = os.path.dirname(os.path.abspath(__file__))
 # sources whose change (with the compiler flags) invalidates a traffic record
 # of the scan kernels
-KERNEL_SOURCES = ("csrc/tile.h", "csrc/scan_cmp.hip", "csrc/scan_crs.hip", "csrc/internal.h", "csrc/traveltime.h")
+KERNEL_SOURCES = ("csrc/tile.h", "csrc/scan_cmp.hip", "csrc/scan_crs.hip", "csrc/scan.hip", "csrc/internal.h",
+                  "csrc/traveltime.h")
 COPY_KERNEL = "copyBuffer"
 
 
@@ -223,6 +230,78 @@ def current_traffic(path: str) -> float | None:
     return float(rec["traffic_bytes_per_launch"])
 
 
+# Per-kernel rates kept in a counter record (the rest of counter_summary's
+# output is context for the reader of the record).
+COUNTER_FIELDS = ("valu_insts_per_wave_eval", "fma_f32_per_wave_eval", "lds_insts_per_wave_eval",
+                  "lds_load_bytes_per_lane_eval", "lds_busy_fraction", "lds_load_bytes_per_clk_per_cu",
+                  "wave_wait_fraction")
+
+
+def counter_record(kernels: dict, csvs) -> dict:
+    """{kernel substring: {field: value}} for every kernel of `kernels`
+    ({substring: intersections per launch}), from rocprofv3 --pmc runs."""
+    out = {}
+    for k, evals in kernels.items():
+        sm = counter_summary([c for c in csvs if _has_kernel(c, k)], k, int(evals))
+        per = sm["counters_per_launch"]
+        rec = {"evals_per_launch": int(evals)}
+        if "SQ_INSTS_VALU_FMA_F32" in per:
+            sm["fma_f32_per_wave_eval"] = per["SQ_INSTS_VALU_FMA_F32"] / sm["wave_evals_per_launch"]
+        for f in COUNTER_FIELDS:
+            if f in sm:
+                rec[f] = sm[f]
+        out[k] = rec
+    return out
+
+
+def _has_kernel(path: str, kernel: str) -> bool:
+    with open(path) as f:
+        return any(kernel in line for line in f)
+
+
+def write_counter_record(rec: dict, path: str, header: str = ""):
+    with open(path, "w") as f:
+        if header:
+            f.write(header.rstrip() + "\n\n")
+        f.write(f"source_digest: {source_digest()}\n")
+        for k, fields in rec.items():
+            f.write(f"\n[{k}]\n")
+            for n, v in fields.items():
+                f.write(f"{n}: {v}\n")
+
+
+def read_counter_record(path: str) -> tuple[str | None, dict]:
+    if not os.path.exists(path):
+        return None, {}
+    digest, cur, out = None, None, {}
+    for line in open(path):
+        line = line.rstrip("\n")
+        if line.startswith("#") or not line.strip():
+            continue
+        if line.startswith("[") and line.endswith("]"):
+            cur = line[1:-1]
+            out[cur] = {}
+        elif ": " in line:
+            k, v = line.split(": ", 1)
+            if cur is None:
+                if k == "source_digest":
+                    digest = v.strip()
+            else:
+                out[cur][k.strip()] = float(v)
+    return digest, out
+
+
+def current_counters(path: str, kernel: str) -> dict | None:
+    """The recorded rates of `kernel`, or None when the record is missing,
+    holds no such kernel or was taken on other kernel sources."""
+    digest, rec = read_counter_record(path)
+    if digest != source_digest() or kernel not in rec:
+        return None
+    r = rec[kernel]
+    need = ("valu_insts_per_wave_eval", "fma_f32_per_wave_eval", "lds_load_bytes_per_lane_eval")
+    return r if all(n in r for n in need) else None
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         print(kernel_stats_table(argv[1]))
@@ -231,6 +310,16 @@ def main(argv):
     elif len(argv) >= 4 and argv[0] == "counters":
         import json
         print(json.dumps(counter_summary(argv[3:], argv[1], int(float(argv[2]))), indent=1))
+    elif len(argv) >= 4 and argv[0] == "counter-record" and "--" in argv:
+        # counter-record <out.txt> <kernel>=<evals> ... -- <csv> ...
+        cut = argv.index("--")
+        kernels = {}
+        for a in argv[2:cut]:
+            k, e = a.rsplit("=", 1)
+            kernels[k] = int(float(e))
+        rec = counter_record(kernels, argv[cut + 1:])
+        write_counter_record(rec, argv[1], header=comment_header(argv[1]))
+        print(open(argv[1]).read())
     elif len(argv) == 6 and argv[0] == "traffic":
         rec = traffic_record(argv[1], argv[2], argv[3], int(argv[4]))
         write_record(rec, argv[5], header=comment_header(argv[5]))

@@ -38,11 +38,30 @@ def test_cmp_valid_count_is_exact():
     assert bench.cmp_valid_evals(gs.half_offset, wl.grid.q, int(gs.ns[0]), gs.dt, wl.w) == v
 
 
-def test_crs_valid_fraction_is_exact():
+def test_crs_valid_count_is_exact():
     wl = synth.crs_line(centrals=[20, 300], grid=synth.crs_coarse_grid())
     v, t = _brute_valid(wl.gathers, wl.jobs, wl.grid, wl.w)
-    f = bench.crs_valid_fraction(wl.gathers, wl.jobs, wl.grid, wl.w, range(wl.jobs.njobs))
-    assert abs(f - v / t) < 1e-15
+    assert bench.valid_windows(wl.gathers, wl.jobs, wl.grid, wl.w, "crs") == v
+    # small chunks: the same count
+    assert bench.valid_windows(wl.gathers, wl.jobs, wl.grid, wl.w, "crs", chunk=1000) == v
+
+
+def test_valid_count_of_uneven_jobs_and_negative_radicands():
+    """Uneven fold and ns (neighbours of another length), CRS with B < 0
+    making T < 0, w = 1 (where T < 0 alone decides) and w = 9, CMP jobs."""
+    from tests import helpers
+    rng = np.random.default_rng(5)
+    gs = helpers.random_line(rng, 6, fold_range=(1, 4), ns_range=(30, 90), hmax=400.0)
+    grid = synth.Grid(A=np.array([-3e-3, 0.0, 2e-3], np.float32), B=np.array([-2e-5, 0.0, 1e-5], np.float32),
+                      q=synth.velocity_grid(700, 3000, 4))
+    for w in (1, 9):
+        jobs = synth.line_crs_jobs(gs, list(range(6)), 2)
+        v, _ = _brute_valid(gs, jobs, grid, w)
+        assert bench.valid_windows(gs, jobs, grid, w, "crs") == v
+        cj = synth.cmp_jobs(gs)
+        cg = synth.Grid(A=np.zeros(1, np.float32), B=np.zeros(1, np.float32), q=grid.q)
+        v, _ = _brute_valid(gs, synth.line_crs_jobs(gs, list(range(6)), 0), cg, w)
+        assert bench.valid_windows(gs, cj, synth.Grid(q=grid.q), w, "cmp") == v
 
 
 def test_eq2_flops():
