@@ -452,12 +452,22 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                                 } else {
                                     T = fma(qd[p], cc, s2e);
                                 }
-                                // tau < 2^30 keeps the conversion exact (floor); the
-                                // NaN that T <= 0 gives (and +inf's) becomes 2^30, a
-                                // window start no trace has: the range test below
-                                // rejects those traces without a test on T
-                                const double tau = fmin(sqrt_newton(T), 1073741824.0);
-                                const int k = (int)tau;
+                                // k = floor(tau) for 0 <= tau < 2^31.  T <= 0 gives a
+                                // NaN or an infinity, which the range test below must
+                                // reject without a test on T.  For HW >= 1 the
+                                // hardware conversion does it: it saturates (+inf and
+                                // tau >= 2^31 give INT_MAX) and turns NaN into 0, and
+                                // both lie outside [HW, lim + HW].  For HW = 0 a NaN
+                                // would give the valid start 0, so tau is first
+                                // clamped to 2^30 (fmin drops the NaN).
+                                double tau = sqrt_newton(T);
+                                int k;
+                                if (HW >= 1) {
+                                    asm("v_cvt_i32_f64 %0, %1" : "=v"(k) : "v"(tau));
+                                } else {
+                                    tau = fmin(tau, 1073741824.0);
+                                    k = (int)tau;
+                                }
                                 if (!((unsigned)(k - HW) <= (unsigned)lim)) continue;
                                 const float x = (float)__builtin_amdgcn_fract(tau);
                                 const float u = 1.f - x;
