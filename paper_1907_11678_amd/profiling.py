@@ -139,16 +139,18 @@ def traffic_record(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int)
 def counter_summary(csvs, kernel: str, evals: int) -> dict:
     """Per-launch SQ counters of the largest-grid dispatches of `kernel` from
     one or more `rocprofv3 --pmc` counter_collection.csv files, and the rates
-    per 64-lane evaluation (evals = intersections per launch)."""
+    per 64-lane evaluation (evals = intersections per launch).  The largest
+    grid is taken over all the files: a file whose launches of the kernel are
+    all smaller (another, smaller workload) adds nothing."""
     acc = defaultdict(float)
     nl = defaultdict(int)
     gui = []
-    for path in csvs:
-        rows = list(csv.DictReader(open(path)))
-        grids = [int(r["Grid_Size"]) for r in rows if kernel in r["Kernel_Name"]]
-        if not grids:
-            raise SystemExit(f"{path}: no dispatch of {kernel!r}")
-        gmax = max(grids)
+    tables = [list(csv.DictReader(open(path))) for path in csvs]
+    grids = [int(r["Grid_Size"]) for rows in tables for r in rows if kernel in r["Kernel_Name"]]
+    if not grids:
+        raise SystemExit(f"{', '.join(csvs)}: no dispatch of {kernel!r}")
+    gmax = max(grids)
+    for rows in tables:
         part = defaultdict(float)
         seen = defaultdict(set)
         for r in rows:

@@ -79,6 +79,21 @@ def test_counter_summary_averages_full_launches_over_passes(tmp_path):
     assert "GRBM_GUI_ACTIVE" not in per
 
 
+def test_counter_summary_ignores_files_of_a_smaller_workload(tmp_path):
+    # the same kernel on a smaller workload (a smaller grid) in another file
+    # must not enter the per-launch average of the full workload's launches
+    evals = 64 * 1000
+    full = _counters(tmp_path / "full.csv", [
+        (1, SCAN, 800, "SQ_INSTS_VALU", 52000.0), (1, SCAN, 800, "GRBM_GUI_ACTIVE", 8 * 2000.0)])
+    small = _counters(tmp_path / "small.csv", [
+        (4, SCAN, 80, "SQ_INSTS_VALU", 5200.0), (4, SCAN, 80, "GRBM_GUI_ACTIVE", 8 * 200.0)])
+    out = profiling.counter_summary([small, full], "scan_kernel<0, 15, 0>", evals)
+    assert out["counters_per_launch"]["SQ_INSTS_VALU"] == pytest.approx(52000.0)
+    assert out["gpu_cycles_per_launch"] == pytest.approx(2000.0)
+    with pytest.raises(SystemExit):
+        profiling.counter_summary([small], "batch_kernel<11, 9, 0>", evals)
+
+
 def test_kernel_trace_table_splits_by_grid(tmp_path):
     p = tmp_path / "t.csv"
     with open(p, "w", newline="") as f:
