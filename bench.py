@@ -48,8 +48,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 vector peak (published)
-# LDS: 128 bytes per clock per CU, 256 CUs, 2.4 GHz
-PEAK_LDS_TBPS = 128 * 256 * 2.4e9 / 1e12
+# LDS: 256 bytes per clock per CU, 256 CUs, 2.4 GHz.  The 16-byte read probe
+# (semb_probe) measures about 145 TB/s, 236 B per clock at the spec clock, so
+# the 128 B per clock of earlier CDNA parts is not this part's figure.
+PEAK_LDS_TBPS = 256 * 256 * 2.4e9 / 1e12
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "scan_kernel_cmp_large_traffic.txt")
 COUNTER_RECORD = os.path.join(ROOT, "profiles", "scan_kernel_counters.txt")
 
@@ -61,6 +63,22 @@ def log(*a):
 def eq2_flops(evals: int, valid: int, w: int) -> int:
     """Eq. 2 work: 12 per intersection, 7w per window on its trace."""
     return 12 * evals + 7 * w * valid
+
+
+CEILINGS: dict = {}
+
+
+def measure_ceilings(semb) -> dict:
+    """The probes of the library: plain FP32 and FP64 FMA rates (TFLOP/s),
+    v_rsq_f64 results (T/s), LDS read bandwidth (TB/s) with 16-byte reads and
+    with the paired 4-byte reads the scan windows use, each the best of 3
+    runs of 5 launches."""
+    out = {}
+    for name, key in (("fma_f32", "fp32_fma_tflops"), ("fma_f64", "fp64_fma_tflops"),
+                      ("rsq_f64", "rsq_f64_tps"), ("lds_read", "lds_read_tbps"),
+                      ("lds_read2", "lds_read2_tbps")):
+        out[key] = max(semb.probe(name, reps=5)[0] for _ in range(3)) / 1e12
+    return out
 
 
 def roofline(kernel: str, evals: int, valid: int, w: int, kernel_ms: float, call_ms: float | None,
@@ -76,7 +94,10 @@ def roofline(kernel: str, evals: int, valid: int, w: int, kernel_ms: float, call
     included).  With a counter record of the same kernel sources (profiles/),
     also the executed rates from the counters, at the live kernel time:
     FP32 FMA work against the FP32 peak, VALU instructions per CU clock (at
-    2.4 GHz), and LDS bytes read against the LDS peak."""
+    2.4 GHz), and LDS bytes read against the LDS peak; and, with the ceilings
+    the probes measured in this run, VALU issue against the plain-FMA issue
+    ceiling and LDS bytes against the measured LDS bandwidth, the larger of
+    which names the binding unit."""
     from paper_1907_11678_amd import profiling
     if flops is None:
         flops = eq2_flops(evals, valid, w)
@@ -97,7 +118,7 @@ def roofline(kernel: str, evals: int, valid: int, w: int, kernel_ms: float, call
         fma = rec["fma_f32_per_wave_eval"] * we * 64 * 2 / t / 1e12
         lds = rec["lds_load_bytes_per_lane_eval"] * evals / t / 1e12
         issue = rec["valu_insts_per_wave_eval"] * we / (t * 2.4e9 * 256)
-        out["executed"] = {
+        ex = {
             "fp32_fma_tflops": fma, "fp32_fma_frac": fma / PEAK_FP32_TFLOPS,
             "valu_insts_per_wave_eval": rec["valu_insts_per_wave_eval"],
             "valu_insts_per_clk_per_cu": issue,
@@ -105,6 +126,18 @@ def roofline(kernel: str, evals: int, valid: int, w: int, kernel_ms: float, call
             "lds_busy_fraction": rec.get("lds_busy_fraction"),
             "binding": "lds" if lds / PEAK_LDS_TBPS > issue else "valu issue",
             "source": os.path.relpath(COUNTER_RECORD, ROOT)}
+        if CEILINGS:
+            # wave-instructions per second: the probe's plain FMAs (2 flops x 64 lanes each)
+            # against every VALU instruction the kernel issued
+            v_ceil = CEILINGS["fp32_fma_tflops"] * 1e12 / 128.0
+            v_rate = rec["valu_insts_per_wave_eval"] * we / t
+            ex["valu_issue_frac_of_measured"] = v_rate / v_ceil
+            ex["fp32_fma_frac_of_measured"] = fma / CEILINGS["fp32_fma_tflops"]
+            # the kernels read their windows with paired 4-byte reads
+            ex["lds_frac_of_measured"] = lds / CEILINGS["lds_read2_tbps"]
+            ex["binding"] = "lds" if ex["lds_frac_of_measured"] > ex["valu_issue_frac_of_measured"] else \
+                "valu issue"
+        out["executed"] = ex
     else:
         out["executed"] = None
     return out
@@ -212,6 +245,8 @@ def main():
                     help="also measure the paper's Table 1 dataset shapes (CMP and CRS)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (counter calibration)")
+    ap.add_argument("--batch-shape", type=int, default=-1, metavar="BS",
+                    help="(profiling) run the batched leg in batch shape BS, split 256, without the tuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -226,6 +261,10 @@ def main():
     torch.cuda.set_device(0)
     dev = "cuda"
     stream = torch.cuda.current_stream()
+
+    # measured ceilings of this part (microbenchmarks), the executed-rate denominators
+    CEILINGS.update(measure_ceilings(semb))
+    log("ceilings: " + ", ".join(f"{k} {v:.4g}" for k, v in CEILINGS.items()))
 
     if args.calibrate_copy > 0:
         nb = args.calibrate_copy << 20
@@ -313,6 +352,7 @@ def main():
             "tile_shape": shape, "tile_shape_ms_on_sample": shape_ms,
         },
         "roofline": rl,
+        "ceilings": dict(CEILINGS, source="semb_probe microbenchmarks, this run"),
     }
     # PCIe context (never `value`): the samples' host-to-device copy from pinned
     # memory, timed on its own after the step, and the rate a caller who
@@ -342,7 +382,7 @@ def main():
         del fine
         torch.cuda.empty_cache()
     if "batched" in legs:
-        out["batched"] = batched_leg(torch, synth, semb, dev, stream)
+        out["batched"] = batched_leg(torch, synth, semb, dev, stream, args.batch_shape)
 
     if args.paper_shapes:
         out["paper_shapes"] = paper_shapes_leg(torch, synth, semb, dev, stream)
@@ -596,7 +636,7 @@ def refine_leg(torch, synth, semb, dev, stream, fine):
     return res
 
 
-def batched_leg(torch, synth, semb, dev, stream):
+def batched_leg(torch, synth, semb, dev, stream, fixed_shape: int = -1):
     t = time.time()
     bw = synth.batched_line()
     log(f"generated the batched line in {time.time() - t:.1f} s")
@@ -613,9 +653,14 @@ def batched_leg(torch, synth, semb, dev, stream):
     st = torch.empty(n, dtype=torch.float32, device=dev)
     # batch tile shape and parameter split, tuned on the first 512 jobs (outside the timed region)
     t = time.time()
-    shape, split, tune_ms = semb.tune_batch(dg, dj, bw.kind, kind, qc, bw.w_cmp, A, B, qr, bw.w_crs, jobs.central,
-                                            jobs.apert_ptr, jobs.apert_gather, gs.ns, gs.trace_ptr, best, sb, st,
-                                            splits=(256, 1024), reps=1, sample_jobs=512, stream=stream)
+    if fixed_shape >= 0:
+        shape, split, tune_ms = fixed_shape, 256, {}
+        semb.set_batch_choice(bw.w_cmp, bw.w_crs, dg, dj, shape, split)
+    else:
+        shape, split, tune_ms = semb.tune_batch(dg, dj, bw.kind, kind, qc, bw.w_cmp, A, B, qr, bw.w_crs,
+                                                jobs.central, jobs.apert_ptr, jobs.apert_gather, gs.ns,
+                                                gs.trace_ptr, best, sb, st, splits=(256, 1024), reps=1,
+                                                sample_jobs=512, stream=stream)
     log(f"batch tile shape {shape} ({semb.batch_shape_name(shape)}), split {split}; ms per shape on the "
         f"512-job sample {tune_ms} ({time.time() - t:.1f} s)")
     tiles, ng, npart = semb.batch_plan(bw.kind, jobs.central, jobs.apert_ptr, jobs.apert_gather, gs.ns,

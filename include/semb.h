@@ -432,7 +432,11 @@ int32_t semb_tuning_load(const char *path);
  * (nullable) receives the longest list, which crs_scan accepts up to
  * SEMB_APERT_LIMIT.  Returns the number of entries, -1 on invalid input
  * (semb_last_error).  A uniform grid hash with cells of the radius's size
- * keeps each query to 3 x 3 cells.  [host] */
+ * keeps each query to 3 x 3 cells.  The CRS operator of crs_scan is the 2D
+ * one (section 2.2): its dm is the difference of the single coordinates in
+ * semb_gathers.midpoint and .central_x.  With y given, the apertures are 2D
+ * but the traveltime still sees only that coordinate: the caller chooses it
+ * (e.g. the inline position), and the crossline distance enters nothing.  [host] */
 int64_t semb_radius_apertures(const double *x, const double *y, int32_t ngathers, const int32_t *centrals,
                               int32_t ncentrals, double radius, int32_t *apert_ptr, int32_t *apert_gather,
                               int32_t *max_apert);
@@ -449,6 +453,30 @@ int64_t semb_radius_apertures(const double *x, const double *y, int32_t ngathers
  * events.  The events belong to the device current at start.  [host] */
 semb_status semb_kernel_timer_start(int32_t capacity);
 semb_status semb_kernel_timer_stop(int32_t *count, float *ms, int32_t ms_len);
+
+/* Microbenchmarks: the ceilings the scan kernels are measured against, taken
+ * on the device current for the calling thread (the roofline analysis of
+ * section 4.3 divides by such peaks).  Each probe launches 8 workgroups per
+ * CU of independent work (a warm-up launch, then `reps` timed launches, HIP
+ * events on a stream of its own) and writes *rate (work per second) and *ms
+ * (mean milliseconds per launch):
+ *   SEMB_PROBE_FMA_F32  plain FP32 FMAs (packed FP32 is not used): flops/s,
+ *                       2 per FMA lane
+ *   SEMB_PROBE_FMA_F64  FP64 FMAs: flops/s, 2 per FMA lane
+ *   SEMB_PROBE_RSQ_F64  v_rsq_f64, the start of every traveltime: lane
+ *                       results per second
+ *   SEMB_PROBE_LDS_READ 16-byte LDS reads without bank conflicts: bytes/s
+ *   SEMB_PROBE_LDS_READ2 paired 4-byte LDS reads (ds_read2_b32) of 16
+ *                       consecutive words per lane, neighbouring lanes one
+ *                       word apart, as a scan window reads them: bytes/s
+ * Allocates and frees a small device buffer; synchronizes its own stream.
+ * SEMB_EINVAL for an unknown probe or reps outside 1..100.  [host] */
+#define SEMB_PROBE_FMA_F32 0
+#define SEMB_PROBE_FMA_F64 1
+#define SEMB_PROBE_RSQ_F64 2
+#define SEMB_PROBE_LDS_READ 3
+#define SEMB_PROBE_LDS_READ2 4
+semb_status semb_probe(int32_t probe, int32_t reps, double *rate, double *ms);
 
 /* Message describing the last non-OK status returned on this thread. [host] */
 const char *semb_last_error(void);

@@ -141,6 +141,8 @@ def lib():
         L.semb_kernel_timer_start.restype = C.c_int
         L.semb_kernel_timer_stop.argtypes = [P, P, i32]
         L.semb_kernel_timer_stop.restype = C.c_int
+        L.semb_probe.argtypes = [i32, i32, P, P]
+        L.semb_probe.restype = C.c_int
         L.semb_last_error.restype = C.c_char_p
         L.semb_version.restype = C.c_char_p
         _lib = L
@@ -153,6 +155,19 @@ def last_error() -> str:
 
 def version() -> str:
     return lib().semb_version().decode()
+
+
+PROBES = {"fma_f32": 0, "fma_f64": 1, "rsq_f64": 2, "lds_read": 3, "lds_read2": 4}
+
+
+def probe(name: str, reps: int = 5) -> tuple[float, float]:
+    """One microbenchmark on the current device: (rate, ms per launch).
+    fma_f32 / fma_f64: flops/s of plain FMAs; rsq_f64: v_rsq_f64 lane
+    results/s; lds_read: LDS bytes read/s with 16-byte reads; lds_read2: the
+    same with the paired 4-byte reads of a scan window."""
+    rate, ms = C.c_double(0.0), C.c_double(0.0)
+    _check(lib().semb_probe(PROBES[name], int(reps), C.byref(rate), C.byref(ms)))
+    return float(rate.value), float(ms.value)
 
 
 def workspace_bytes(nsamples: int) -> int:
@@ -431,7 +446,9 @@ def alloc_workspace(nsamples: int, device="cuda"):
 # ---------------------------------------------------------------------------
 def radius_apertures(x, centrals, radius: float, y=None):
     """(apert_ptr, apert_gather, max_apert) of the gathers within `radius` of
-    each central's midpoint (x[, y] per gather, metres)."""
+    each central's midpoint (x[, y] per gather, metres).  crs_scan's
+    traveltime is the 2D CRS one: it measures dm along the one coordinate the
+    gathers' midpoint / central_x hold, whatever y did to the apertures."""
     import numpy as np
     x = np.ascontiguousarray(x, np.float64)
     yv = None if y is None else np.ascontiguousarray(y, np.float64)

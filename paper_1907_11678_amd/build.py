@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsemb.so")
-SOURCES = ["api.cpp", "aperture.cpp", "scan.hip", "scan_cmp.hip", "scan_crs.hip", "point.hip"]
+SOURCES = ["api.cpp", "aperture.cpp", "scan.hip", "scan_cmp.hip", "scan_crs.hip", "point.hip", "probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,6 +1,7 @@
 // api.cpp -- host side of the C ABI declared in include/semb.h: argument
 // validation, workspace carving, launch configuration and error reporting.
-// Nothing here allocates device memory or synchronises a stream.
+// Apart from the tuners and the probes, nothing here allocates device memory
+// or synchronises a stream.
 
 #include <math.h>
 #include <stdarg.h>
@@ -16,6 +17,10 @@
 #include <vector>
 
 #include "internal.h"
+
+namespace semb {
+int run_probe(int probe, int reps, double *rate, double *ms);  // probe.hip
+}
 
 namespace {
 
@@ -740,6 +745,14 @@ semb_status semb_kernel_timer_stop(int32_t *count, float *ms, int32_t ms_len)
     }
     t.release();
     return st;
+}
+
+semb_status semb_probe(int32_t probe, int32_t reps, double *rate, double *ms)
+{
+    if (probe < SEMB_PROBE_FMA_F32 || probe > SEMB_PROBE_LDS_READ2) return fail(SEMB_EINVAL, "unknown probe");
+    if (reps < 1 || reps > 100) return fail(SEMB_EINVAL, "reps must be in 1..100");
+    if (!rate || !ms) return fail(SEMB_EINVAL, "rate and ms are required");
+    return hip_status((hipError_t)semb::run_probe(probe, reps, rate, ms), "semb_probe");
 }
 
 semb_status semb_corrected_gathers(const semb_gathers *g, const semb_jobs *jobs, int32_t kind, const float *theta,

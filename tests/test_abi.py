@@ -142,6 +142,19 @@ def test_noalloc_scan_validates(semb):
                                None) == 1  # CRS without A, B
 
 
+def test_probe_validates(semb):
+    """semb_probe rejects unknown probes, reps outside 1..100 and missing
+    outputs before it touches the device."""
+    L = semb.lib()
+    r, m = C.c_double(), C.c_double()
+    assert L.semb_probe(5, 5, C.byref(r), C.byref(m)) == 1
+    assert L.semb_probe(-1, 5, C.byref(r), C.byref(m)) == 1
+    assert L.semb_probe(0, 0, C.byref(r), C.byref(m)) == 1
+    assert L.semb_probe(0, 101, C.byref(r), C.byref(m)) == 1
+    assert L.semb_probe(0, 5, None, C.byref(m)) == 1
+    assert set(semb.PROBES) == {"fma_f32", "fma_f64", "rsq_f64", "lds_read", "lds_read2"}
+
+
 def test_point_calls_validate(semb):
     L = semb.lib()
     g = _gathers(semb)
