@@ -79,3 +79,33 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_roofline_executed_fractions(tmp_path, monkeypatch):
+    """The executed object: rates from a counter record (matching digest) at
+    the live kernel time, against the published peaks and the probes'
+    ceilings, and the unit nearer its measured ceiling named as binding."""
+    from paper_1907_11678_amd import profiling
+    rec = {"scan_kernel<0, 15, 0>": {"evals_per_launch": 64e6, "valu_insts_per_wave_eval": 50.0,
+                                     "fma_f32_per_wave_eval": 32.0, "lds_load_bytes_per_lane_eval": 80.0,
+                                     "lds_busy_fraction": 0.8}}
+    path = str(tmp_path / "counters.txt")
+    profiling.write_counter_record(rec, path)
+    monkeypatch.setattr(bench, "COUNTER_RECORD", path)
+    monkeypatch.setattr(bench, "CEILINGS", {"fp32_fma_tflops": 128.0, "lds_read2_tbps": 80.0})
+    evals, t_ms = 64_000_000, 1.0  # 1e6 wave-evaluations in 1 ms
+    r = bench.roofline("scan_kernel<0, 15, 0>", evals, evals, 15, t_ms, 2.0)
+    ex = r["executed"]
+    assert r["frac"] == bench.eq2_flops(evals, evals, 15) / 1e-3 / 1e12 / bench.PEAK_FP32_TFLOPS
+    assert r["frac_whole_call"] == r["frac"] / 2
+    assert abs(ex["fp32_fma_tflops"] - 32.0 * 1e6 * 64 * 2 / 1e-3 / 1e12) < 1e-9        # 4.096
+    assert abs(ex["lds_tbps"] - 80.0 * evals / 1e-3 / 1e12) < 1e-9                       # 5.12
+    assert abs(ex["valu_issue_frac_of_measured"] - (50.0 * 1e6 / 1e-3) / (128e12 / 128)) < 1e-12  # 0.05
+    assert abs(ex["lds_frac_of_measured"] - 5.12 / 80.0) < 1e-12                         # 0.064
+    assert ex["binding"] == "lds"
+    monkeypatch.setattr(bench, "CEILINGS", {"fp32_fma_tflops": 64.0, "lds_read2_tbps": 80.0})
+    assert bench.roofline("scan_kernel<0, 15, 0>", evals, evals, 15, t_ms, None)["executed"]["binding"] == "valu issue"
+    # another kernel, or a record of other sources, gives no executed object
+    assert bench.roofline("scan_kernel<1, 9, 2>", evals, evals, 9, t_ms, None)["executed"] is None
+    monkeypatch.setattr(profiling, "source_digest", lambda: "0000000000000000")
+    assert bench.roofline("scan_kernel<0, 15, 0>", evals, evals, 15, t_ms, None)["executed"] is None
