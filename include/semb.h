@@ -222,6 +222,15 @@ semb_status semb_theta_from_best(const int32_t *best, int64_t n_out, const float
                                  const float *B, int32_t nB, const float *q, int32_t nq, float *theta,
                                  hipStream_t stream);
 
+/* theta[row][k] = min(max(theta[row][k] + d[k], lo[k]), hi[k]) for n rows of
+ * theta [n][3] (device FP32, in place); d, lo, hi: host [3].  Places further
+ * starts of a multi-start refinement beside a coarse peak: the continuous
+ * ascent that replaces section 3.2's fine grid climbs the maximum of its
+ * start's basin, and a coarse grid can put a side lobe of the wavelet and
+ * the main lobe in one cell.  SEMB_EINVAL if lo > hi or d is not finite. */
+semb_status semb_theta_shift(float *theta, int64_t n, const float *d, const float *lo, const float *hi,
+                             hipStream_t stream);
+
 /* Gathers corrected along each output row's parameter theta[row] = (A, B, q)
  * (the NMO / CRS correction at the picks, for quality control): for job j,
  * aperture trace r (gathers as listed, traces in order) and output sample

@@ -20,6 +20,8 @@
 
 namespace semb {
 int run_probe(int probe, int reps, double *rate, double *ms);  // probe.hip
+hipError_t launch_theta_shift(float *theta, int64_t n, const float *d, const float *lo, const float *hi,
+                              hipStream_t stream);  // point.hip
 }
 
 namespace {
@@ -707,6 +709,17 @@ semb_status semb_theta_from_best(const int32_t *best, int64_t n_out, const float
         return fail(SEMB_EINVAL, "too many parameters");
     return hip_status(semb::launch_theta_from_best(best, n_out, A, A ? nA : 1, B, B ? nB : 1, q, nq, theta, stream),
                       "semb_theta_from_best launch");
+}
+
+semb_status semb_theta_shift(float *theta, int64_t n, const float *d, const float *lo, const float *hi,
+                             hipStream_t stream)
+{
+    if (n < 0) return fail(SEMB_EINVAL, "semb_theta_shift: n must be >= 0");
+    if (n == 0) return SEMB_OK;
+    if (!theta || !d || !lo || !hi) return fail(SEMB_EINVAL, "semb_theta_shift: theta, d, lo and hi are required");
+    for (int k = 0; k < 3; ++k)
+        if (!(lo[k] <= hi[k]) || !isfinite(d[k])) return fail(SEMB_EINVAL, "semb_theta_shift: need lo <= hi, finite d");
+    return hip_status(semb::launch_theta_shift(theta, n, d, lo, hi, stream), "semb_theta_shift launch");
 }
 
 semb_status semb_kernel_timer_start(int32_t capacity)

@@ -332,6 +332,17 @@ __global__ void theta_from_best_kernel(const int32_t *best, int64_t n, const flo
     }
 }
 
+// theta[i] = clamp(theta[i] + d, lo, hi) per component: a further start of a
+// multi-start refinement beside a coarse peak.
+__global__ void theta_shift_kernel(float *theta, int64_t n, float3 d, float3 lo, float3 hi)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        theta[3 * i + 0] = fminf(fmaxf(theta[3 * i + 0] + d.x, lo.x), hi.x);
+        theta[3 * i + 1] = fminf(fmaxf(theta[3 * i + 1] + d.y, lo.y), hi.y);
+        theta[3 * i + 2] = fminf(fmaxf(theta[3 * i + 2] + d.z, lo.z), hi.z);
+    }
+}
+
 // Gathers corrected along each output sample's parameter (quality control):
 // lane l reads every aperture trace at the intersection of its row, with the
 // interpolation of a one-sample window, and writes it to the job's corrected
@@ -578,6 +589,17 @@ hipError_t launch_theta_from_best(const int32_t *best, int64_t n, const float *A
     const long long nb = (n + 255) / 256;
     hipLaunchKernelGGL(theta_from_best_kernel, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, stream, best,
                        n, A, nA, B, nB, q, nq, theta);
+    return hipGetLastError();
+}
+
+hipError_t launch_theta_shift(float *theta, int64_t n, const float *d, const float *lo, const float *hi,
+                              hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const long long nb = (n + 255) / 256;
+    hipLaunchKernelGGL(theta_shift_kernel, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, stream, theta, n,
+                       make_float3(d[0], d[1], d[2]), make_float3(lo[0], lo[1], lo[2]),
+                       make_float3(hi[0], hi[1], hi[2]));
     return hipGetLastError();
 }
 

@@ -142,6 +142,21 @@ def test_noalloc_scan_validates(semb):
                                None) == 1  # CRS without A, B
 
 
+def test_theta_shift_validates(semb):
+    """semb_theta_shift rejects a negative n, missing arrays, lo > hi and a
+    non-finite shift before it touches the device; n = 0 is a no-op."""
+    L = semb.lib()
+    f3 = C.c_float * 3
+    P = C.c_void_p(0x4000)
+    ok = (f3(0, 0, 1), f3(-1, -1, -1), f3(1, 1, 1))
+    assert L.semb_theta_shift(P, 0, *ok, None) == 0
+    assert L.semb_theta_shift(P, -1, *ok, None) == 1
+    assert L.semb_theta_shift(None, 4, *ok, None) == 1
+    assert L.semb_theta_shift(P, 4, f3(0, 0, 1), f3(-1, 2, -1), f3(1, 1, 1), None) == 1
+    assert L.semb_theta_shift(P, 4, f3(0, float("nan"), 1), f3(-1, -1, -1), f3(1, 1, 1), None) == 1
+    assert L.semb_theta_shift(P, 4, None, f3(-1, -1, -1), f3(1, 1, 1), None) == 1
+
+
 def test_probe_validates(semb):
     """semb_probe rejects unknown probes, reps outside 1..100 and missing
     outputs before it touches the device."""

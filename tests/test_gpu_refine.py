@@ -107,30 +107,34 @@ def test_refinement_is_monotone_and_reports_its_semblance():
 
 
 def test_refinement_reaches_the_fine_grid():
-    """Coarse 7x7x11 scan, its 4 best local maxima per row as starts, 32 sign
-    steps from each (the bench's rule), against the exhaustive 21x21x41 scan.
-    The refined S reaches the fine grid's (within 1e-4) on at least 85% of
-    the rows (S_fine > 0.1) and the 5th percentile of the gap is above -0.02.
-    The rows short by more than 0.01 are reported with how many have no start
-    within one coarse cell of the fine grid's optimum (a basin the coarse
-    grid's peaks miss)."""
+    """Coarse 7x7x11 scan, the library's multi-start rule (its 2 best local
+    maxima per row, each also shifted by +-0.3 and +-0.6 coarse cells in q,
+    16 sign steps from each of the 10 starts; the bench's rule), against the
+    exhaustive 21x21x41 scan.  The refined S reaches the fine grid's (within
+    1e-4) on at least 90% of the rows (S_fine > 0.1), and the 5th percentile
+    of the gap is at least -0.01 (FP64 CPU model of the same rule on this
+    slice: 95.7% and 0.0).  The rows short by more than 0.01 are reported
+    with how many have no start within one coarse cell of the fine grid's
+    optimum (a basin the coarse grid's peaks miss)."""
     import torch
     import paper_1907_11678_amd as semb
     wl = synth.crs_line(centrals=[120, 121])
-    r = Refinement(wl, steps=32)
-    n, K, coarse = r.n, 4, r.coarse
+    r = Refinement(wl, steps=semb.MULTISTART_STEPS)
+    n, K, coarse = r.n, semb.MULTISTART_PEAKS, r.coarse
+    offs = semb.MULTISTART_OFFSETS
+    NS = K * len(offs)
     panel = torch.empty((n, coarse.n), device="cuda")
     semb.crs_scan(r.dg, r.dj, r.A, r.B, r.q, wl.w, r.best, r.s0, r.st0, r.ws, panel=panel)
-    theta_k = torch.empty((K, n, 3), device="cuda")
-    s_k = torch.empty((K, n), device="cuda")
-    st_k = torch.empty((K, n), device="cuda")
+    theta_k = torch.empty((NS, n, 3), device="cuda")
+    s_k = torch.empty((NS, n), device="cuda")
+    st_k = torch.empty((NS, n), device="cuda")
     best_k = torch.empty((K, n), dtype=torch.int32, device="cuda")
     peak_s = torch.empty((K, n), device="cuda")
     S = torch.empty(n, device="cuda")
     st = torch.empty(n, device="cuda")
     th = torch.empty((n, 3), device="cuda")
     semb.refine_multistart(r.dg, r.dj, 1, panel, r.A, r.B, r.q, wl.w, K, theta_k, s_k, st_k, best_k, peak_s, S, st,
-                           th, steps=r.steps, eta0=0.5, scale=r.scale, lo=r.lo, hi=r.hi)
+                           th, steps=r.steps, eta0=0.5, scale=r.scale, lo=r.lo, hi=r.hi, offsets=offs)
     fine = gu.run_scan("crs", wl.gathers, wl.jobs, wl.grid, wl.w, dg=r.dg, dj=r.dj)
     torch.cuda.synchronize()
     Sr = S.cpu().numpy().astype(np.float64)
@@ -138,14 +142,15 @@ def test_refinement_reaches_the_fine_grid():
     sel = Sf > 0.1
     d = (Sr - Sf)[sel]
     thf = oracle.theta_of(wl.grid, fine[0], "crs")
-    starts = np.stack([oracle.theta_of(coarse, b, "crs") for b in best_k.cpu().numpy()])
+    peaks = [oracle.theta_of(coarse, b, "crs") for b in best_k.cpu().numpy()]
+    starts = np.stack([np.clip(p + np.asarray(o) * np.asarray(r.scale), r.lo, r.hi) for p in peaks for o in offs])
     dist = (np.abs(starts - thf[None]) / np.asarray(r.scale)).max(axis=2).min(axis=0)
     short = sel & (Sr < Sf - 0.01)
     _say(f"refined - fine-grid S over {sel.sum()} rows: median {np.median(d):+.4f}, "
          f"p5 {np.percentile(d, 5):+.4f}, >= -1e-4: {(d >= -1e-4).mean():.3f}; short by > 0.01: "
          f"{int(short.sum())}, of them with no start within one coarse cell: {int((short & (dist > 1)).sum())}")
-    assert (d >= -1e-4).mean() >= 0.85
-    assert np.percentile(d, 5) > -0.02
+    assert (d >= -1e-4).mean() >= 0.90
+    assert np.percentile(d, 5) >= -0.01
 
 
 def test_refinement_graph_replay():
@@ -250,8 +255,10 @@ def test_panel_peaks_match_reference():
 
 
 def test_multistart_refinement_is_never_worse():
-    """K = 3 starts from the coarse panel's peaks: candidate 0 is the coarse pick,
-    so the best of three is at least the single-start result on every row."""
+    """K = 3 peaks of the coarse panel, each also shifted by +-0.5 coarse cells
+    in q: candidate 0 is the coarse pick, so the best of the nine is at least
+    the single-start result on every row; each shifted start is its peak's
+    grid parameters plus the shift, clamped to the box, in FP32."""
     import torch
     import paper_1907_11678_amd as semb
     wl = synth.crs_line(centrals=[180, 181])
@@ -261,19 +268,30 @@ def test_multistart_refinement_is_never_worse():
     single = r.S.cpu().numpy().copy()
     coarse = r.coarse
     n, K = r.n, 3
+    offs = ((0.0, 0.0, 0.0), (0.0, 0.0, -0.5), (0.0, 0.0, 0.5))
+    NS = K * len(offs)
     panel = torch.empty((n, coarse.n), device="cuda")
     semb.crs_scan(r.dg, r.dj, r.A, r.B, r.q, wl.w, r.best, r.s0, r.st0, r.ws, panel=panel)
-    theta_k = torch.empty((K, n, 3), device="cuda")
-    s_k = torch.empty((K, n), device="cuda")
-    st_k = torch.empty((K, n), device="cuda")
+    theta_k = torch.empty((NS, n, 3), device="cuda")
+    s_k = torch.empty((NS, n), device="cuda")
+    st_k = torch.empty((NS, n), device="cuda")
     best_k = torch.empty((K, n), dtype=torch.int32, device="cuda")
     peak_s = torch.empty((K, n), device="cuda")
     S = torch.empty(n, device="cuda")
     st = torch.empty(n, device="cuda")
     th = torch.empty((n, 3), device="cuda")
     semb.refine_multistart(r.dg, r.dj, 1, panel, r.A, r.B, r.q, wl.w, K, theta_k, s_k, st_k, best_k, peak_s, S, st,
-                           th, steps=r.steps, eta0=0.5, scale=r.scale, lo=r.lo, hi=r.hi)
+                           th, steps=r.steps, eta0=0.5, scale=r.scale, lo=r.lo, hi=r.hi, offsets=offs)
+    # the shifted starts of peak 1 against numpy in FP32
+    t1 = torch.empty((n, 3), device="cuda")
+    semb.theta_from_best(best_k[1], r.q, t1, A=r.A, B=r.B)
+    base = t1.cpu().numpy()
+    semb.theta_shift(t1, (0.0, 0.0, 0.5 * r.scale[2]), r.lo, r.hi)
     torch.cuda.synchronize()
+    want = base.copy()
+    want[:, 2] = np.minimum(np.maximum(base[:, 2] + np.float32(0.5 * r.scale[2]), np.float32(r.lo[2])),
+                            np.float32(r.hi[2]))
+    assert np.array_equal(t1.cpu().numpy(), want)
     assert np.array_equal(best_k[0].cpu().numpy(), r.best.cpu().numpy())
     assert np.array_equal(s_k[0].cpu().numpy(), single)
     Sm = S.cpu().numpy()
