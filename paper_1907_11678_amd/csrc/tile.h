@@ -420,7 +420,14 @@ __device__ __forceinline__ void scan_tile(const GatherView &g, const JobView &jv
                 double qd[P];  // this wave's parameters (CMP), held in scalar registers
 #pragma unroll
                 for (int p = 0; p < P; ++p) qd[p] = to_sgpr(L.pq[wv * P + p]);
-                if (lane_on) {
+                // CMP: a wave whose parameters all lie past the block's end (the
+                // last block of a ragged grid) has nothing to add; it only keeps
+                // the barriers, and its SIMD slots go to the other workgroups
+                // (measured 1.1% on the CMP-large scan and 2.5% on CMP plain; the
+                // CRS grids' last blocks are a negligible share, and there the
+                // test cost more than it saved)
+                const bool wave_on = CRS || pb + wv * P < pend;
+                if (lane_on && wave_on) {
                     for (int r = 0; r < nfit; ++r) {
                         // one LDS load per trace: lim and off, and for CMP cc (the
                         // empty asm keeps the optimiser from splitting the load
