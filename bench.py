@@ -245,6 +245,8 @@ def main():
                     help="also measure the paper's Table 1 dataset shapes (CMP and CRS)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (counter calibration)")
+    ap.add_argument("--plain-shape", type=int, default=-1, metavar="S",
+                    help="(profiling) run the CMP-plain leg in tile shape S without the tuner")
     ap.add_argument("--batch-shape", type=int, default=-1, metavar="BS",
                     help="(profiling) run the batched leg in batch shape BS, split 256, without the tuner")
     args = ap.parse_args()
@@ -374,7 +376,7 @@ def main():
 
     legs = set() if args.cmp_only else {x.strip() for x in args.legs.split(",") if x.strip()}
     if "cmp_plain" in legs:
-        out["cmp_plain"] = cmp_plain_leg(torch, synth, semb, dev, stream)
+        out["cmp_plain"] = cmp_plain_leg(torch, synth, semb, dev, stream, fixed_shape=args.plain_shape)
     if legs & {"crs", "refine"}:
         out["crs"], fine = crs_leg(torch, synth, semb, dev, stream)
         if "refine" in legs:
@@ -433,7 +435,7 @@ def _timed_replays(torch, g, stream, n):
     return [e0.elapsed_time(e1) for e0, e1 in ev]
 
 
-def cmp_plain_leg(torch, synth, semb, dev, stream, launches: int = 20):
+def cmp_plain_leg(torch, synth, semb, dev, stream, launches: int = 20, fixed_shape: int = -1):
     """64 midpoints x fold 24 x 1000 samples (dt 4 ms), 101 velocities, w 11:
     a call of about a tenth of a millisecond, so `launches` back-to-back
     cmp_scan calls are captured in one HIP graph and replayed; time per call =
@@ -450,7 +452,11 @@ def cmp_plain_leg(torch, synth, semb, dev, stream, launches: int = 20):
     ws = semb.alloc_workspace(dg.nsamples)
     q = torch.from_numpy(wl.grid.q).to(dev)
     s = torch.cuda.Stream()
-    shape, _ = semb.tune_scan(0, dg, dj, q, wl.w, best, sb, st, ws, sample_jobs=64, reps=5, stream=s)
+    if fixed_shape >= 0:
+        shape = fixed_shape
+        semb.set_scan_shape(0, wl.w, dg, dj, shape)
+    else:
+        shape, _ = semb.tune_scan(0, dg, dj, q, wl.w, best, sb, st, ws, sample_jobs=64, reps=5, stream=s)
     with semb.KernelTimer(launches) as kt:
         for _ in range(launches):
             semb.cmp_scan(dg, dj, q, wl.w, best, sb, st, ws, stream=s)
