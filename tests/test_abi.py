@@ -157,6 +157,15 @@ def test_theta_shift_validates(semb):
     assert L.semb_theta_shift(P, 4, None, f3(-1, -1, -1), f3(1, 1, 1), None) == 1
 
 
+def test_multistart_requires_the_unshifted_start_first(semb):
+    """refine_multistart refuses offsets whose first entry is not zero (start 0
+    must be the scan's own pick) before it touches the device."""
+    with pytest.raises(ValueError):
+        semb.refine_multistart(None, None, 1, None, None, None, None, 9, 2, None, None, None, None, None, None,
+                               None, None, offsets=((0.0, 0.0, 0.3), (0.0, 0.0, 0.0)))
+    assert all(v == 0.0 for v in semb.MULTISTART_OFFSETS[0])
+
+
 def test_probe_validates(semb):
     """semb_probe rejects unknown probes, reps outside 1..100 and missing
     outputs before it touches the device."""
