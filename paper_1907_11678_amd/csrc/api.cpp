@@ -1151,18 +1151,32 @@ int32_t semb_tuning_load(const char *path)
     char line[256];
     int lineno = 0;
     bool bad = false;
+    // a window the scans accept, and a power-of-two bucket index
+    auto ok_w = [](int w) { return w >= 1 && w <= SEMB_W_MAX && (w & 1); };
+    auto ok_bucket = [](int b) { return b >= 0 && b <= 40; };  // log2_bucket's range
     while (fgets(line, sizeof line, f)) {
         ++lineno;
-        if (line[0] == '#' || line[0] == '\n') continue;
-        int a[6];
-        if (sscanf(line, "scan %d %d %d %d %d", &a[0], &a[1], &a[2], &a[3], &a[4]) == 5) {
-            if ((a[0] != SEMB_KIND_CMP && a[0] != SEMB_KIND_CRS) || a[4] < 0 || a[4] >= semb::kScanShapes) {
+        const size_t len = strlen(line);
+        if (len == sizeof line - 1 && line[len - 1] != '\n') {  // longer than any entry
+            bad = true;
+            break;
+        }
+        const char *p = line;
+        while (*p == ' ' || *p == '\t' || *p == '\r' || *p == '\n') ++p;
+        if (*p == '#' || *p == '\0') continue;
+        int a[6], end = -1;
+        if (sscanf(p, "scan %d %d %d %d %d %n", &a[0], &a[1], &a[2], &a[3], &a[4], &end) == 5 && end > 0 &&
+            p[end] == '\0') {
+            if ((a[0] != SEMB_KIND_CMP && a[0] != SEMB_KIND_CRS) || !ok_w(a[1]) || !ok_bucket(a[2]) ||
+                !ok_bucket(a[3]) || a[4] < 0 || a[4] >= semb::kScanShapes) {
                 bad = true;
                 break;
             }
             scans[ShapeKey{a[0], a[1], a[2], a[3]}] = a[4];
-        } else if (sscanf(line, "batch %d %d %d %d %d %d", &a[0], &a[1], &a[2], &a[3], &a[4], &a[5]) == 6) {
-            if (a[4] < 0 || a[4] >= semb::kBatchShapes || a[5] < 1) {
+        } else if (sscanf(p, "batch %d %d %d %d %d %d %n", &a[0], &a[1], &a[2], &a[3], &a[4], &a[5], &end) == 6 &&
+                   end > 0 && p[end] == '\0') {
+            if (!ok_w(a[0]) || !ok_w(a[1]) || !ok_bucket(a[2]) || !ok_bucket(a[3]) || a[4] < 0 ||
+                a[4] >= semb::kBatchShapes || a[5] < 1) {
                 bad = true;
                 break;
             }

@@ -405,9 +405,18 @@ def test_tuning_table_round_trip(semb, tmp_path):
     with pytest.raises(semb.SembError):
         semb.load_tuning(str(bad))
     assert L.semb_scan_shape(0, 15, C.byref(g2), C.byref(j1)) == 3  # unchanged
-    bad.write_text("batch 11 9 5 10 7 256\n")  # shape out of range
-    with pytest.raises(semb.SembError):
-        semb.load_tuning(str(bad))
+    for text in ("batch 11 9 5 10 7 256\n",        # shape out of range
+                 "scan 0 15 6 11 1 extra\n",       # trailing words
+                 "scan 0 14 6 11 1\n",             # an even window
+                 "batch 11 9 -1 10 0 256\n",       # a negative bucket
+                 "scan 0 15 6 11 1" + " " * 300 + "\n"):  # longer than any entry
+        bad.write_text(text)
+        with pytest.raises(semb.SembError):
+            semb.load_tuning(str(bad))
+    assert L.semb_scan_shape(0, 15, C.byref(g2), C.byref(j1)) == 3  # still unchanged
+    ok = tmp_path / "ok.txt"
+    ok.write_text("# a comment\n\n   \n  scan 0 15 6 11 2  \r\n")  # blank lines, spaces, CRLF
+    assert semb.load_tuning(str(ok)) == 1
     with pytest.raises(semb.SembError):
         semb.load_tuning(str(tmp_path / "missing.txt"))
     L.semb_clear_tuning()
