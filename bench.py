@@ -28,8 +28,8 @@ Prints one JSON line.  Fields beyond the step itself:
   refine        the CRS line again: a coarse 7 x 7 x 11 scan + 8 gradient-
                 ascent steps per output sample, captured in one HIP graph,
                 against the exhaustive 21 x 21 x 41 scan (time and semblance);
-                also from the 2 best local maxima of the coarse panel, each
-                also shifted in q, 16 steps per start (multistart);
+                also from the 4 best local maxima of the coarse panel, the
+                best two also shifted in q, 16 steps per start (multistart);
   cpu_baseline  the FP64 oracle on this host's cores over the first gathers
                 of the CMP-large workload (same per-intersection metric).
 """
@@ -590,8 +590,8 @@ def refine_leg(torch, synth, semb, dev, stream, fine):
     # multi-start: the coarse scan's panel, its best local maxima per row, each
     # also shifted along q, as starts (the library's rule); the best of all
     # ascents; one graph
-    K, OFFS, STEPS_MS = semb.MULTISTART_PEAKS, semb.MULTISTART_OFFSETS, semb.MULTISTART_STEPS
-    NS = K * len(OFFS)
+    K, STARTS, STEPS_MS = semb.MULTISTART_PEAKS, semb.MULTISTART_STARTS, semb.MULTISTART_STEPS
+    NS = len(STARTS)
     panel = torch.empty((n, coarse.n), device=dev)
     theta_k = torch.empty((NS, n, 3), device=dev)
     s_k = torch.empty((NS, n), device=dev)
@@ -605,7 +605,7 @@ def refine_leg(torch, synth, semb, dev, stream, fine):
     def run_ms():
         semb.crs_scan(dg, dj, A, B, q, wl.w, best, s0, st0, ws, panel=panel, stream=s)
         semb.refine_multistart(dg, dj, 1, panel, A, B, q, wl.w, K, theta_k, s_k, st_k, best_k, peak_s, Sm, stm,
-                               thm, steps=STEPS_MS, eta0=0.5, scale=scale, lo=lo, hi=hi, stream=s, offsets=OFFS)
+                               thm, steps=STEPS_MS, eta0=0.5, scale=scale, lo=lo, hi=hi, stream=s, starts=STARTS)
 
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -625,23 +625,23 @@ def refine_leg(torch, synth, semb, dev, stream, fine):
     semb.theta_from_best(torch.from_numpy(fine["best"]).to(dev), torch.from_numpy(wl.grid.q).to(dev), thf,
                          A=torch.from_numpy(wl.grid.A).to(dev), B=torch.from_numpy(wl.grid.B).to(dev))
     th_starts = theta_k.clone()
-    for k in range(K):  # the starts themselves (theta_k now holds the refined ones)
-        for o, off in enumerate(OFFS):
-            semb.theta_from_best(best_k[k], q, th_starts[k * len(OFFS) + o], A=A, B=B)
-            if o > 0:
-                semb.theta_shift(th_starts[k * len(OFFS) + o], [off[c] * scale[c] for c in range(3)], lo, hi)
+    for i, (k, off) in enumerate(STARTS):  # the starts themselves (theta_k now holds the refined ones)
+        semb.theta_from_best(best_k[k], q, th_starts[i], A=A, B=B)
+        if any(off):
+            semb.theta_shift(th_starts[i], [off[c] * scale[c] for c in range(3)], lo, hi)
     torch.cuda.synchronize()
     sc = np.asarray(scale, np.float64)
     dist = np.min(np.abs(th_starts.cpu().numpy().astype(np.float64) - thf.cpu().numpy()[None]) / sc, axis=0).max(1)
     short = (Sm.cpu().numpy().astype(np.float64) - Sf < -0.01) & sel
-    res["multistart"] = {"peaks": K, "q_offsets_in_coarse_cells": [o[2] for o in OFFS], "starts": NS,
+    res["multistart"] = {"peaks": K, "starts_peak_and_offset_in_coarse_cells": [[k, list(o)] for k, o in STARTS],
+                         "starts": NS,
                            "steps": STEPS_MS, "ms": m_ms, "speedup_vs_exhaustive": fine["ms"] / m_ms,
                            "s_gap_median": float(np.median(dm_)), "s_gap_p5": float(np.percentile(dm_, 5)),
                            "s_gap_mean": float(dm_.mean()), "frac_at_least_fine": float((dm_ >= -1e-4).mean()),
                            "rows_short_by_0.01": int(short.sum()),
                            "short_rows_with_no_start_within_1_coarse_cell": int((short & (dist > 1.0)).sum())}
     res["s_gap_mean"] = float(d.mean())
-    log(f"refine, {K} peaks x {len(OFFS)} q offsets x {STEPS_MS} steps: {m_ms:.1f} ms; S gap median {np.median(dm_):+.4f}, "
+    log(f"refine, {NS} starts from {K} peaks x {STEPS_MS} steps: {m_ms:.1f} ms; S gap median {np.median(dm_):+.4f}, "
         f"mean {dm_.mean():+.4f}, p5 {np.percentile(dm_, 5):+.4f}, >= fine-1e-4 on {(dm_ >= -1e-4).mean():.3f}; "
         f"{int(short.sum())} rows short by > 0.01, {int((short & (dist > 1.0)).sum())} of them with no start "
         f"within one coarse cell of the fine grid's optimum")

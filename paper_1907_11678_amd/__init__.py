@@ -761,46 +761,53 @@ def best_of(s_k, stack_k, theta_k, s_out, stack_out, theta_out, stream=None):
                               _typed(theta_out, torch.float32, "theta_out"), _stream(stream)))
 
 
-# The multi-start rule the bench and the tests use: the 2 best local maxima of
-# the coarse panel, each also shifted by -0.3, +0.3, -0.6 and +0.6 coarse
-# cells in q, 16 sign steps from each of the 10 starts.  Chosen on the CPU
-# with the FP64 oracle on 4 CRS-line centrals (40, 140, 260, 380): 93.4% of
-# the rows end within 1e-4 of the fine grid's S (5th percentile of the gap
-# -0.0014), against 88.7% (-0.038) for the 4 best peaks with 32 steps each,
-# for 160 instead of 128 start-steps.  Shifts along q reach the side lobes
-# of the wavelet that share a coarse cell with the main lobe.
-MULTISTART_PEAKS = 2
-MULTISTART_OFFSETS = ((0.0, 0.0, 0.0), (0.0, 0.0, -0.3), (0.0, 0.0, 0.3), (0.0, 0.0, -0.6), (0.0, 0.0, 0.6))
+# The multi-start rule the bench and the tests use: the 4 best local maxima
+# of the coarse panel; the best two each also shifted by -0.3, +0.3, -0.6 and
+# +0.6 coarse cells in q; 16 sign steps from each of the 12 starts.  Chosen on
+# the CPU with the FP64 oracle on 4 CRS-line centrals (40, 140, 260, 380):
+# 94.3% of the rows end within 1e-4 of the fine grid's S (5th percentile of
+# the gap -0.0003), against 88.7% (-0.038) for the 4 best peaks with 32 steps
+# each, for 192 instead of 128 start-steps.  Shifts along q reach the side
+# lobes of the wavelet that share a coarse cell with the main lobe; the third
+# and fourth peaks reach basins the best two miss.
+MULTISTART_PEAKS = 4
+_Q_SHIFTS = ((0.0, 0.0, 0.0), (0.0, 0.0, -0.3), (0.0, 0.0, 0.3), (0.0, 0.0, -0.6), (0.0, 0.0, 0.6))
+MULTISTART_STARTS = tuple((k, o) for k in (0, 1) for o in _Q_SHIFTS) + ((2, _Q_SHIFTS[0]), (3, _Q_SHIFTS[0]))
 MULTISTART_STEPS = 16
 
 
 def refine_multistart(g: DeviceGathers, jobs: DeviceJobs, kind: int, panel, A, B, q, w: int, K: int, theta_k,
                       s_k, stack_k, best_k, peak_s, s_out, stack_out, theta_out, steps: int = 8,
                       eta0: float = 0.5, scale=(1.0, 1.0, 1.0), lo=(-1e30, -1e30, -1e30), hi=(1e30, 1e30, 1e30),
-                      grow: float = 1.2, stream=None, offsets=((0.0, 0.0, 0.0),)):
-    """Refinement from the K best local maxima of a coarse scan's panel: peaks,
-    then one ascent from each peak shifted by each of `offsets` (in units of
-    `scale`, clamped to [lo, hi]; offsets[0] must be zero, so that start 0 is
-    the scan's own pick), then the best of the K * len(offsets) results.
-    Scratch tensors: theta_k [K * len(offsets), n, 3], s_k, stack_k
-    [K * len(offsets), n] (FP32), best_k [K, n] (int32), peak_s [K, n] (FP32)."""
-    if any(float(v) != 0.0 for v in offsets[0]):
-        raise ValueError("offsets[0] must be (0, 0, 0)")
+                      grow: float = 1.2, stream=None, offsets=((0.0, 0.0, 0.0),), starts=None):
+    """Refinement from the K best local maxima of a coarse scan's panel:
+    peaks, then one ascent from each start, then the best of them.  A start
+    is (peak index < K, offset): the peak's grid parameters shifted by offset
+    (in units of `scale`, clamped to [lo, hi]).  `starts` lists them; by
+    default every peak with every one of `offsets`.  The first start must be
+    (0, zero), the scan's own pick, so the result is never worse than a
+    single start.  Scratch tensors: theta_k [len(starts), n, 3], s_k, stack_k
+    [len(starts), n] (FP32), best_k [K, n] (int32), peak_s [K, n] (FP32)."""
+    if starts is None:
+        starts = [(k, o) for k in range(K) for o in offsets]
+    starts = [(int(k), tuple(float(v) for v in o)) for k, o in starts]
+    if not starts or starts[0][0] != 0 or any(v != 0.0 for v in starts[0][1]):
+        raise ValueError("the first start must be peak 0 unshifted")
+    if any(k < 0 or k >= K for k, _ in starts):
+        raise ValueError(f"a start names a peak outside 0..{K - 1}")
+    ns = len(starts)
+    if int(theta_k.shape[0]) < ns or int(s_k.shape[0]) < ns or int(stack_k.shape[0]) < ns:
+        raise ValueError(f"theta_k, s_k and stack_k need {ns} starts")
     nA = int(A.numel()) if A is not None else 1
     nB = int(B.numel()) if B is not None else 1
-    no = len(offsets)
-    if int(theta_k.shape[0]) < K * no or int(s_k.shape[0]) < K * no or int(stack_k.shape[0]) < K * no:
-        raise ValueError(f"theta_k, s_k and stack_k need K * len(offsets) = {K * no} starts")
     panel_peaks(panel, nA, nB, int(q.numel()), K, best_k, peak_s, stream=stream)
-    for k in range(K):
-        for o, off in enumerate(offsets):
-            i = k * no + o
-            theta_from_best(best_k[k], q, theta_k[i], A=A, B=B, stream=stream)
-            if o > 0:
-                theta_shift(theta_k[i], [float(off[c]) * float(scale[c]) for c in range(3)], lo, hi, stream=stream)
-            refine(g, jobs, kind, theta_k[i], w, s_k[i], stack_k[i], steps=steps, eta0=eta0, scale=scale, lo=lo,
-                   hi=hi, grow=grow, stream=stream)
-    best_of(s_k[:K * no], stack_k[:K * no], theta_k[:K * no], s_out, stack_out, theta_out, stream=stream)
+    for i, (k, off) in enumerate(starts):
+        theta_from_best(best_k[k], q, theta_k[i], A=A, B=B, stream=stream)
+        if any(v != 0.0 for v in off):
+            theta_shift(theta_k[i], [off[c] * float(scale[c]) for c in range(3)], lo, hi, stream=stream)
+        refine(g, jobs, kind, theta_k[i], w, s_k[i], stack_k[i], steps=steps, eta0=eta0, scale=scale, lo=lo,
+               hi=hi, grow=grow, stream=stream)
+    best_of(s_k[:ns], stack_k[:ns], theta_k[:ns], s_out, stack_out, theta_out, stream=stream)
 
 
 def _semblance_at_class():

@@ -163,7 +163,12 @@ def test_multistart_requires_the_unshifted_start_first(semb):
     with pytest.raises(ValueError):
         semb.refine_multistart(None, None, 1, None, None, None, None, 9, 2, None, None, None, None, None, None,
                                None, None, offsets=((0.0, 0.0, 0.3), (0.0, 0.0, 0.0)))
-    assert all(v == 0.0 for v in semb.MULTISTART_OFFSETS[0])
+    with pytest.raises(ValueError):  # a peak the panel search does not return
+        semb.refine_multistart(None, None, 1, None, None, None, None, 9, 2, None, None, None, None, None, None,
+                               None, None, starts=((0, (0, 0, 0)), (2, (0, 0, 0))))
+    k0, o0 = semb.MULTISTART_STARTS[0]
+    assert k0 == 0 and all(v == 0.0 for v in o0)
+    assert max(k for k, _ in semb.MULTISTART_STARTS) < semb.MULTISTART_PEAKS
 
 
 def test_probe_validates(semb):

@@ -107,22 +107,22 @@ def test_refinement_is_monotone_and_reports_its_semblance():
 
 
 def test_refinement_reaches_the_fine_grid():
-    """Coarse 7x7x11 scan, the library's multi-start rule (its 2 best local
-    maxima per row, each also shifted by +-0.3 and +-0.6 coarse cells in q,
-    16 sign steps from each of the 10 starts; the bench's rule), against the
-    exhaustive 21x21x41 scan.  The refined S reaches the fine grid's (within
-    1e-4) on at least 90% of the rows (S_fine > 0.1), and the 5th percentile
-    of the gap is at least -0.01 (FP64 CPU model of the same rule on this
-    slice: 95.7% and 0.0).  The rows short by more than 0.01 are reported
-    with how many have no start within one coarse cell of the fine grid's
-    optimum (a basin the coarse grid's peaks miss)."""
+    """Coarse 7x7x11 scan, the library's multi-start rule (its 4 best local
+    maxima per row, the best two also shifted by +-0.3 and +-0.6 coarse cells
+    in q, 16 sign steps from each of the 12 starts; the bench's rule),
+    against the exhaustive 21x21x41 scan.  The refined S reaches the fine
+    grid's (within 1e-4) on at least 90% of the rows (S_fine > 0.1), and the
+    5th percentile of the gap is at least -0.01 (FP64 CPU model of the 10-start
+    rule on this slice: 95.7% and 0.0).  The rows short by more than 0.01 are
+    reported with how many have no start within one coarse cell of the fine
+    grid's optimum (a basin the coarse grid's peaks miss)."""
     import torch
     import paper_1907_11678_amd as semb
     wl = synth.crs_line(centrals=[120, 121])
     r = Refinement(wl, steps=semb.MULTISTART_STEPS)
     n, K, coarse = r.n, semb.MULTISTART_PEAKS, r.coarse
-    offs = semb.MULTISTART_OFFSETS
-    NS = K * len(offs)
+    starts_rule = semb.MULTISTART_STARTS
+    NS = len(starts_rule)
     panel = torch.empty((n, coarse.n), device="cuda")
     semb.crs_scan(r.dg, r.dj, r.A, r.B, r.q, wl.w, r.best, r.s0, r.st0, r.ws, panel=panel)
     theta_k = torch.empty((NS, n, 3), device="cuda")
@@ -134,7 +134,7 @@ def test_refinement_reaches_the_fine_grid():
     st = torch.empty(n, device="cuda")
     th = torch.empty((n, 3), device="cuda")
     semb.refine_multistart(r.dg, r.dj, 1, panel, r.A, r.B, r.q, wl.w, K, theta_k, s_k, st_k, best_k, peak_s, S, st,
-                           th, steps=r.steps, eta0=0.5, scale=r.scale, lo=r.lo, hi=r.hi, offsets=offs)
+                           th, steps=r.steps, eta0=0.5, scale=r.scale, lo=r.lo, hi=r.hi, starts=starts_rule)
     fine = gu.run_scan("crs", wl.gathers, wl.jobs, wl.grid, wl.w, dg=r.dg, dj=r.dj)
     torch.cuda.synchronize()
     Sr = S.cpu().numpy().astype(np.float64)
@@ -143,7 +143,7 @@ def test_refinement_reaches_the_fine_grid():
     d = (Sr - Sf)[sel]
     thf = oracle.theta_of(wl.grid, fine[0], "crs")
     peaks = [oracle.theta_of(coarse, b, "crs") for b in best_k.cpu().numpy()]
-    starts = np.stack([np.clip(p + np.asarray(o) * np.asarray(r.scale), r.lo, r.hi) for p in peaks for o in offs])
+    starts = np.stack([np.clip(peaks[k] + np.asarray(o) * np.asarray(r.scale), r.lo, r.hi) for k, o in starts_rule])
     dist = (np.abs(starts - thf[None]) / np.asarray(r.scale)).max(axis=2).min(axis=0)
     short = sel & (Sr < Sf - 0.01)
     _say(f"refined - fine-grid S over {sel.sum()} rows: median {np.median(d):+.4f}, "
