@@ -181,6 +181,59 @@ def test_refinement_graph_replay():
             assert np.array_equal(a_, e_), f"replay {k}"
 
 
+def test_multistart_graph_replay():
+    """The whole multi-start rule (coarse scan with panel, peaks, shifted
+    starts, ascents, best of) captured in one graph: three replays, with
+    eager work and cleared outputs in between, equal the eager run bit for
+    bit."""
+    import torch
+    import paper_1907_11678_amd as semb
+    wl = synth.crs_line(centrals=[210])
+    r = Refinement(wl, steps=semb.MULTISTART_STEPS)
+    n, K, coarse = r.n, semb.MULTISTART_PEAKS, r.coarse
+    starts = semb.MULTISTART_STARTS
+    NS = len(starts)
+    panel = torch.empty((n, coarse.n), device="cuda")
+    theta_k = torch.empty((NS, n, 3), device="cuda")
+    s_k = torch.empty((NS, n), device="cuda")
+    st_k = torch.empty((NS, n), device="cuda")
+    best_k = torch.empty((K, n), dtype=torch.int32, device="cuda")
+    peak_s = torch.empty((K, n), device="cuda")
+    S = torch.empty(n, device="cuda")
+    st = torch.empty(n, device="cuda")
+    th = torch.empty((n, 3), device="cuda")
+
+    def run(stream=None):
+        semb.crs_scan(r.dg, r.dj, r.A, r.B, r.q, wl.w, r.best, r.s0, r.st0, r.ws, panel=panel, stream=stream)
+        semb.refine_multistart(r.dg, r.dj, 1, panel, r.A, r.B, r.q, wl.w, K, theta_k, s_k, st_k, best_k, peak_s, S,
+                               st, th, steps=r.steps, eta0=0.5, scale=r.scale, lo=r.lo, hi=r.hi, stream=stream,
+                               starts=starts)
+
+    run()
+    torch.cuda.synchronize()
+    eager = (th.cpu().numpy(), S.cpu().numpy(), st.cpu().numpy())
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        run(stream=s)
+    for k in range(3):
+        th.fill_(0.0)
+        S.fill_(-1.0)
+        theta_k.fill_(0.0)
+        torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = (th.cpu().numpy(), S.cpu().numpy(), st.cpu().numpy())
+        for a_, e_ in zip(got, eager):
+            assert np.array_equal(a_, e_), f"replay {k}"
+
+
 def test_autograd_wrapper_matches_oracle_gradient():
     import torch
     import paper_1907_11678_amd as semb
